@@ -30,6 +30,10 @@ def _load():
         lib.oracle_twiddles.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]
         lib.oracle_twiddles.restype = ctypes.c_int
+        lib.oracle_dft_points.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int]
+        lib.oracle_dft_points.restype = ctypes.c_int
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -60,6 +64,18 @@ def dft(x, sign: int = FORWARD, threads: int = 0) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"oracle_dft failed with code {rc}")
     return out[0] if squeeze else out
+
+
+def dft_points(x, ks, sign: int = FORWARD, threads: int = 0) -> np.ndarray:
+    """Outputs y[k] for k in `ks` of the DFT of the 1-D vector `x` (complex128)."""
+    x = np.ascontiguousarray(np.asarray(x).reshape(-1), dtype=np.complex128)
+    ks = np.ascontiguousarray(np.asarray(ks, dtype=np.int64).reshape(-1))
+    out = np.empty(len(ks), np.complex128)
+    rc = _load().oracle_dft_points(x.ctypes.data, len(x), int(sign), ks.ctypes.data, len(ks),
+                                   out.ctypes.data, int(threads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_dft_points failed with code {rc}")
+    return out
 
 
 def twiddles(n: int, sign: int = FORWARD) -> np.ndarray:

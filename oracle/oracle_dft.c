@@ -156,3 +156,54 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * Selected outputs of one transform, straight from the definition:
+ *   out[i] = sum_j x[j] w_N^{j k_i},  k_i = ks[i],  i < nk
+ * (same table, exponent reduction, products and compensated sums as
+ * oracle_dft).  For checking long transforms one output at a time.
+ * Returns 0, -1 on a bad argument (k outside [0, n)), -2 on allocation failure.
+ */
+int oracle_dft_points(const double *in, int64_t n, int sign, const int64_t *ks, int64_t nk,
+                      double *out, int threads)
+{
+    if (n < 1 || nk < 0 || (sign != 1 && sign != -1) || !in || (nk && (!ks || !out)))
+        return -1;
+    for (int64_t i = 0; i < nk; ++i)
+        if (ks[i] < 0 || ks[i] >= n)
+            return -1;
+    double *wr = (double *)malloc(sizeof(double) * (size_t)n);
+    double *wi = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!wr || !wi) {
+        free(wr);
+        free(wi);
+        return -2;
+    }
+    oracle_twiddles(n, sign, wr, wi);
+#ifdef _OPENMP
+    if (threads > 0)
+        omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < nk; ++i) {
+        const int64_t k = ks[i];
+        double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+        int64_t idx = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double a = in[2 * j], bb = in[2 * j + 1];
+            const double c = wr[idx], d = wi[idx];
+            neumaier(&sr, &cr, a * c - bb * d);
+            neumaier(&si, &ci, a * d + bb * c);
+            idx += k;
+            if (idx >= n)
+                idx -= n;
+        }
+        out[2 * i] = sr + cr;
+        out[2 * i + 1] = si + ci;
+    }
+    free(wr);
+    free(wi);
+    return 0;
+}

@@ -83,3 +83,24 @@ def test_bad_arguments():
         oracle.dft(np.zeros((2, 0), np.complex128))
     with pytest.raises(RuntimeError):
         oracle.dft(np.zeros(4, np.complex128), sign=0)
+
+
+def test_points_match_full_transform():
+    # the sampled-output entry point against the full transform, bit for bit
+    g = np.random.default_rng(8)
+    for n in (1, 7, 96, 1000):
+        x = g.uniform(-1, 1, n) + 1j * g.uniform(-1, 1, n)
+        ks = np.unique(np.r_[0, n - 1, g.integers(0, n, 10)])
+        for sign in (-1, 1):
+            assert np.array_equal(oracle.dft_points(x, ks, sign), oracle.dft(x, sign)[ks])
+    with pytest.raises(RuntimeError):
+        oracle.dft_points(np.zeros(4), [4])
+
+
+def test_points_large_n_against_numpy():
+    g = np.random.default_rng(9)
+    n = 1 << 16
+    x = g.uniform(-1, 1, n) + 1j * g.uniform(-1, 1, n)
+    ks = np.array([0, 1, 12345, n - 1])
+    ref = np.fft.fft(x)[ks]
+    assert np.abs(oracle.dft_points(x, ks) - ref).max() / np.abs(ref).max() < 1e-13
