@@ -1,0 +1,133 @@
+/*
+ * fftc -- batched one-dimensional complex FFTs on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper, Section II): for each transform of length N,
+ *     y = DFT_N x,   DFT_N[m, n] = w_N^{m n},   w_N = exp(-2 pi i / N),
+ * computed by the Cooley-Tukey factorisation of Eq. 2,
+ *     DFT_N = (DFT_K (x) I_M) D^N_M (I_K (x) DFT_M) Pi^N_K,   N = M K,
+ * applied recursively in Stockham order (no separate bit-reversal pass).
+ * The inverse direction uses w_N^{-1} and is not scaled (inverse(forward(x))
+ * = N x); the paper defines only the forward transform.
+ *
+ * Conventions shared by every entry point:
+ *  - Layout: interleaved complex (re, im), transforms contiguous and
+ *    batch-major: element (b, j) of a plan with length N is at index b N + j.
+ *    complex64 = two floats (8 bytes, 8-byte aligned), complex128 = two
+ *    doubles (16 bytes, 16-byte aligned).
+ *  - Device pointers are HIP device allocations on the current device; the
+ *    caller owns them.  `stream` is a hipStream_t passed as void* (NULL = the
+ *    default stream).
+ *  - Every call returns an fftc_status; no call aborts, exits or throws.
+ *    A non-OK status leaves a human-readable message for the calling thread
+ *    in fftc_last_error().
+ *  - Supported lengths: 1 <= N <= 2^20 whose prime factors are all <= 7.
+ */
+#ifndef FFTC_H
+#define FFTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FFTC_OK = 0,
+    FFTC_ERR_INVALID_ARG = 1,      /* null / misaligned pointer, bad enum, batch < 1 ... */
+    FFTC_ERR_UNSUPPORTED_SIZE = 2, /* N < 1, N > 2^20, or a prime factor > 7 */
+    FFTC_ERR_OUT_OF_MEMORY = 3,    /* a device or host allocation failed */
+    FFTC_ERR_TOO_LARGE = 4,        /* request larger than the server's memory budget */
+    FFTC_ERR_HIP = 5,              /* a HIP runtime call failed (text in fftc_last_error) */
+    FFTC_ERR_SHUTDOWN = 6,         /* server not running / stopped before completion */
+    FFTC_ERR_INTERNAL = 7
+} fftc_status;
+
+/* Sign of the exponent. */
+enum { FFTC_FORWARD = -1, FFTC_INVERSE = +1 };
+
+/* Element type and arithmetic of a plan. */
+enum {
+    FFTC_C64 = 0,  /* complex64 in and out, fp32 arithmetic, twiddles made in fp64 */
+    FFTC_C128 = 1  /* complex128 in and out, fp64 arithmetic */
+};
+
+/* Plan variants reported by fftc_plan_describe. */
+enum {
+    FFTC_VARIANT_SINGLE_SPECIALISED = 0, /* one kernel compiled for this N and radix list */
+    FFTC_VARIANT_SINGLE_GENERIC = 1,     /* one kernel, runtime N and radix list */
+    FFTC_VARIANT_TWO_PASS = 2            /* Eq. 2 four-step in two kernels + scratch */
+};
+
+typedef struct fftc_plan_s *fftc_plan_t;
+
+/*
+ * Create a plan for `batch` transforms of length `n`.
+ *   direction: FFTC_FORWARD or FFTC_INVERSE;  dtype: FFTC_C64 or FFTC_C128.
+ * The radix list comes from the tuning database when it holds an entry for
+ * (n, dtype), else from the built-in heuristic.  Allocates the plan's twiddle
+ * tables (generated in fp64 on the GPU of the current device) and, for
+ * two-pass plans, its scratch buffer; synchronises once before returning.
+ * On success *plan_out owns these until fftc_destroy_plan.
+ */
+fftc_status fftc_plan(int64_t n, int64_t batch, int direction, int dtype, fftc_plan_t *plan_out);
+
+/*
+ * As fftc_plan with an explicit Stockham radix list r[0..count) whose
+ * product is n; every radix must be one of 2, 3, 4, 5, 7, 8, 16.  Only
+ * single-kernel lengths (see fftc_max_single_n) are accepted.
+ */
+fftc_status fftc_plan_radices(int64_t n, int64_t batch, int direction, int dtype,
+                              const int *radices, int count, fftc_plan_t *plan_out);
+
+/*
+ * Enqueue the plan's transforms on `stream`: in and out are device arrays of
+ * batch * n elements.  in == out (in place) is allowed; other overlaps are
+ * not.  Asynchronous: returns after the launch.  A plan may be executed on
+ * several streams at once, except a two-pass plan, whose calls must be
+ * ordered (they share the plan's scratch).
+ */
+fftc_status fftc_execute(fftc_plan_t plan, const void *in, void *out, void *stream);
+
+/* Free the plan's device memory.  NULL is a no-op.  The caller must ensure
+ * no execution of the plan is still in flight. */
+fftc_status fftc_destroy_plan(fftc_plan_t plan);
+
+/* What a plan runs.  radices[] holds the Stockham radix list (for two-pass
+ * plans: the list of the first pass, then of the second). */
+typedef struct {
+    int64_t n, batch;
+    int direction, dtype;
+    int variant;          /* FFTC_VARIANT_* */
+    int nradices;
+    int radices[16];
+    int threads_per_transform;
+    int transforms_per_group;
+    int64_t split_m, split_k;  /* two-pass: n = m k; else 0 */
+    size_t twiddle_bytes, scratch_bytes;
+} fftc_plan_desc;
+
+fftc_status fftc_plan_describe(fftc_plan_t plan, fftc_plan_desc *desc);
+
+/*
+ * Host-only: the radix list fftc_plan would choose for (n, dtype), without a
+ * GPU.  Writes at most max_count radices and the count.  For two-pass
+ * lengths, the list covers the first pass then the second (see split_m).
+ */
+fftc_status fftc_factorize(int64_t n, int dtype, int *radices, int max_count, int *count,
+                           int64_t *split_m);
+
+/* Host-only: largest n that runs as one kernel for dtype. */
+int64_t fftc_max_single_n(int dtype);
+
+/* Text of a status code (static storage). */
+const char *fftc_status_string(fftc_status s);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *fftc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTC_H */

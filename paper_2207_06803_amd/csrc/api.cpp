@@ -1,0 +1,299 @@
+// C ABI: plans, execution, errors.  No exception crosses this boundary.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "plan.h"
+
+namespace fftc {
+
+static thread_local std::string t_last_error;
+
+fftc_status fail(fftc_status s, const std::string& msg) {
+    t_last_error = msg;
+    return s;
+}
+
+fftc_status fail_hip(hipError_t e, const char* what) {
+    t_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    return e == hipErrorOutOfMemory ? FFTC_ERR_OUT_OF_MEMORY : FFTC_ERR_HIP;
+}
+
+void clear_error() { t_last_error.clear(); }
+
+fftc_status enable_large_lds();
+int two_pass_cols(int dtype);
+
+const SpecEntry* find_spec(int dtype, int64_t n, const std::vector<int>& rs) {
+    int cnt = 0;
+    const SpecEntry* tab = dtype == FFTC_C128 ? spec_table_c128(&cnt) : spec_table_c64(&cnt);
+    for (int i = 0; i < cnt; ++i) {
+        const SpecEntry& e = tab[i];
+        if (e.n != n || e.nr != (int)rs.size()) continue;
+        bool same = true;
+        for (int q = 0; q < e.nr; ++q) same = same && e.radices[q] == rs[q];
+        if (same) return &e;
+    }
+    return nullptr;
+}
+
+static size_t csize_of(int dtype) { return dtype == FFTC_C128 ? 16 : 8; }
+
+static fftc_status check_radices(int64_t n, const std::vector<int>& rs) {
+    int64_t prod = 1;
+    for (int r : rs) {
+        if (r != 2 && r != 3 && r != 4 && r != 5 && r != 7 && r != 8 && r != 16)
+            return fail(FFTC_ERR_INVALID_ARG, "radix " + std::to_string(r) + " not in {2,3,4,5,7,8,16}");
+        prod *= r;
+    }
+    if ((int)rs.size() > kMaxStages) return fail(FFTC_ERR_INVALID_ARG, "too many stages");
+    if (prod != n) return fail(FFTC_ERR_INVALID_ARG, "radices do not multiply to n");
+    return FFTC_OK;
+}
+
+static std::vector<int> choose_radices(int64_t n, int dtype) {
+    std::vector<int> rs;
+    if (tune_lookup(n, dtype, &rs)) return rs;
+    auto c = radix_candidates(n, 1);
+    return c.empty() ? rs : c[0];
+}
+
+// Shape a single-kernel transform of length n with list rs.
+static fftc_status shape_single(fftc_plan_s* p, const std::vector<int>& rs) {
+    const size_t cs = csize_of(p->dtype);
+    p->radices = rs;
+    p->spec = find_spec(p->dtype, p->n, rs);
+    if (p->spec) {
+        p->tpt = p->spec->tpt;
+        p->t = p->spec->t;
+        p->variant = FFTC_VARIANT_SINGLE_SPECIALISED;
+    } else {
+        launch_shape(p->n, rs, (int)cs, &p->tpt, &p->t);
+        p->variant = FFTC_VARIANT_SINGLE_GENERIC;
+    }
+    if (p->tpt * p->t > 1024) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "radix list needs more than 1024 threads");
+    p->lds_bytes = rs.size() > 1 ? (size_t)p->t * lds_len((int)p->n) * cs : 0;
+    if (p->lds_bytes > (size_t)kLdsMaxPerGroup) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "transform too large for LDS");
+    fill_gen_desc(p->n, rs, p->tpt, p->t, 0, &p->gdesc);
+    return FFTC_OK;
+}
+
+static fftc_status alloc_tables(fftc_plan_s* p, const std::vector<TwSegment>& segs, int64_t entries) {
+    const size_t cs = csize_of(p->dtype);
+    p->tw_bytes = (size_t)std::max<int64_t>(entries, 1) * cs;
+    FFTC_HIP_TRY(hipMalloc(&p->tw, p->tw_bytes));
+    return make_twiddles(p->tw, p->dtype, segs, nullptr);
+}
+
+static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype, const int* radices,
+                             int count, fftc_plan_t* out) {
+    clear_error();
+    if (!out) return fail(FFTC_ERR_INVALID_ARG, "plan_out is NULL");
+    *out = nullptr;
+    if (direction != FFTC_FORWARD && direction != FFTC_INVERSE)
+        return fail(FFTC_ERR_INVALID_ARG, "direction must be FFTC_FORWARD (-1) or FFTC_INVERSE (+1)");
+    if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "dtype must be FFTC_C64 or FFTC_C128");
+    if (batch < 1) return fail(FFTC_ERR_INVALID_ARG, "batch must be >= 1");
+    if (n < 1 || n > max_total_n(dtype) || !is_7smooth(n))
+        return fail(FFTC_ERR_UNSUPPORTED_SIZE,
+                    "n = " + std::to_string(n) + " unsupported (need 1 <= n <= 2^20 with prime factors <= 7)");
+    if (batch > (int64_t(1) << 40) / n) return fail(FFTC_ERR_INVALID_ARG, "batch * n too large");
+    if (radices && n > max_single_n(dtype))
+        return fail(FFTC_ERR_INVALID_ARG, "explicit radix lists are for single-kernel lengths only");
+    if (radices) {  // validate before touching the device
+        if (count < 0 || count > kMaxStages || (count == 0 && n != 1))
+            return fail(FFTC_ERR_INVALID_ARG, "bad radix count");
+        fftc_status cr = check_radices(n, std::vector<int>(radices, radices + count));
+        if (cr != FFTC_OK) return cr;
+    }
+    fftc_status st = enable_large_lds();
+    if (st != FFTC_OK) return st;
+
+    fftc_plan_s* p = new (std::nothrow) fftc_plan_s();
+    if (!p) return fail(FFTC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->n = n;
+    p->batch = batch;
+    p->direction = direction;
+    p->dtype = dtype;
+    hipGetDevice(&p->device);
+    const size_t cs = csize_of(dtype);
+
+    if (n <= max_single_n(dtype)) {
+        std::vector<int> rs;
+        if (radices) {
+            rs.assign(radices, radices + count);
+        } else {
+            rs = choose_radices(n, dtype);
+        }
+        // DFT_1 is the identity: an empty radix list (the kernel copies)
+        if (st == FFTC_OK && n == 1) rs.clear();
+        if (st == FFTC_OK && n > 1 && rs.empty()) st = fail(FFTC_ERR_UNSUPPORTED_SIZE, "no factorisation");
+        if (st == FFTC_OK) st = shape_single(p, rs);
+        if (st == FFTC_OK) {
+            std::vector<TwSegment> segs;
+            const int64_t entries = stage_segments(rs, 0, &segs);
+            st = alloc_tables(p, segs, entries);
+        }
+    } else {
+        int64_t m = 0, k = 0;
+        if (!two_pass_split(n, dtype, &m, &k)) st = fail(FFTC_ERR_UNSUPPORTED_SIZE, "no two-pass split");
+        if (st == FFTC_OK) {
+            p->variant = FFTC_VARIANT_TWO_PASS;
+            p->m = m;
+            p->k = k;
+            p->r1 = choose_radices(m, dtype);
+            p->r2 = choose_radices(k, dtype);
+            const int tc = two_pass_cols(dtype);
+            int tpt1, tpt2, tdummy;
+            launch_shape(m, p->r1, (int)cs, &tpt1, &tdummy);
+            launch_shape(k, p->r2, (int)cs, &tpt2, &tdummy);
+            if (tpt1 * tc > 1024 || tpt2 * tc > 1024 ||
+                (size_t)tc * lds_len((int)std::max(m, k)) * cs > (size_t)kLdsMaxPerGroup)
+                st = fail(FFTC_ERR_UNSUPPORTED_SIZE, "two-pass tile does not fit a workgroup");
+            if (st == FFTC_OK) {
+                std::vector<TwSegment> segs;
+                p->tw1_off = 0;
+                const int64_t e1 = stage_segments(p->r1, 0, &segs);
+                p->tw2_off = e1;
+                const int64_t e2 = stage_segments(p->r2, e1, &segs);
+                p->twn_off = e1 + e2;
+                segs.push_back({p->twn_off, n, n, n});
+                fill_gen_desc(m, p->r1, tpt1, tc, p->tw1_off, &p->pass1);
+                fill_gen_desc(k, p->r2, tpt2, tc, p->tw2_off, &p->pass2);
+                p->radices = p->r1;
+                p->radices.insert(p->radices.end(), p->r2.begin(), p->r2.end());
+                p->tpt = tpt1;
+                p->t = tc;
+                st = alloc_tables(p, segs, p->twn_off + n);
+            }
+            if (st == FFTC_OK) {
+                p->scratch_bytes = (size_t)batch * (size_t)n * cs;
+                hipError_t e = hipMalloc(&p->scratch, p->scratch_bytes);
+                if (e != hipSuccess) st = fail_hip(e, "hipMalloc(two-pass scratch)");
+            }
+        }
+    }
+    if (st != FFTC_OK) {
+        std::string keep = t_last_error;
+        fftc_destroy_plan(p);
+        t_last_error = keep;
+        return st;
+    }
+    *out = p;
+    return FFTC_OK;
+}
+
+}  // namespace fftc
+
+using namespace fftc;
+
+extern "C" {
+
+const char* fftc_status_string(fftc_status s) {
+    switch (s) {
+        case FFTC_OK: return "FFTC_OK";
+        case FFTC_ERR_INVALID_ARG: return "FFTC_ERR_INVALID_ARG";
+        case FFTC_ERR_UNSUPPORTED_SIZE: return "FFTC_ERR_UNSUPPORTED_SIZE";
+        case FFTC_ERR_OUT_OF_MEMORY: return "FFTC_ERR_OUT_OF_MEMORY";
+        case FFTC_ERR_TOO_LARGE: return "FFTC_ERR_TOO_LARGE";
+        case FFTC_ERR_HIP: return "FFTC_ERR_HIP";
+        case FFTC_ERR_SHUTDOWN: return "FFTC_ERR_SHUTDOWN";
+        case FFTC_ERR_INTERNAL: return "FFTC_ERR_INTERNAL";
+    }
+    return "FFTC_ERR_UNKNOWN";
+}
+
+const char* fftc_last_error(void) { return t_last_error.c_str(); }
+
+fftc_status fftc_plan(int64_t n, int64_t batch, int direction, int dtype, fftc_plan_t* plan_out) {
+    try {
+        return plan_impl(n, batch, direction, dtype, nullptr, 0, plan_out);
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_plan");
+    }
+}
+
+fftc_status fftc_plan_radices(int64_t n, int64_t batch, int direction, int dtype, const int* radices,
+                              int count, fftc_plan_t* plan_out) {
+    if (!radices) return fail(FFTC_ERR_INVALID_ARG, "radices is NULL");
+    try {
+        return plan_impl(n, batch, direction, dtype, radices, count, plan_out);
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_plan_radices");
+    }
+}
+
+fftc_status fftc_execute(fftc_plan_t p, const void* in, void* out, void* stream) {
+    clear_error();
+    if (!p) return fail(FFTC_ERR_INVALID_ARG, "plan is NULL");
+    if (!in || !out) return fail(FFTC_ERR_INVALID_ARG, "in/out is NULL");
+    const uintptr_t align = p->dtype == FFTC_C128 ? 16 : 8;
+    if (((uintptr_t)in % align) || ((uintptr_t)out % align))
+        return fail(FFTC_ERR_INVALID_ARG, "in/out not aligned to the complex element size");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->variant == FFTC_VARIANT_TWO_PASS) return launch_two_pass(p, in, out, s);
+    return launch_single(p, in, out, s);
+}
+
+fftc_status fftc_destroy_plan(fftc_plan_t p) {
+    if (!p) return FFTC_OK;
+    fftc_status st = FFTC_OK;
+    if (p->tw) {
+        hipError_t e = hipFree(p->tw);
+        if (e != hipSuccess) st = fail_hip(e, "hipFree(twiddles)");
+    }
+    if (p->scratch) {
+        hipError_t e = hipFree(p->scratch);
+        if (e != hipSuccess) st = fail_hip(e, "hipFree(scratch)");
+    }
+    delete p;
+    return st;
+}
+
+fftc_status fftc_plan_describe(fftc_plan_t p, fftc_plan_desc* d) {
+    if (!p || !d) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
+    memset(d, 0, sizeof(*d));
+    d->n = p->n;
+    d->batch = p->batch;
+    d->direction = p->direction;
+    d->dtype = p->dtype;
+    d->variant = p->variant;
+    d->nradices = (int)std::min<size_t>(p->radices.size(), 16);
+    for (int i = 0; i < d->nradices; ++i) d->radices[i] = p->radices[i];
+    d->threads_per_transform = p->tpt;
+    d->transforms_per_group = p->t;
+    d->split_m = p->m;
+    d->split_k = p->k;
+    d->twiddle_bytes = p->tw_bytes;
+    d->scratch_bytes = p->scratch_bytes;
+    return FFTC_OK;
+}
+
+fftc_status fftc_factorize(int64_t n, int dtype, int* radices, int max_count, int* count, int64_t* split_m) {
+    clear_error();
+    if (!count || (max_count > 0 && !radices)) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
+    if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
+    if (n < 1 || n > max_total_n(dtype) || !is_7smooth(n)) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "unsupported n");
+    std::vector<int> rs;
+    int64_t m = 0, k = 0;
+    if (n <= max_single_n(dtype)) {
+        if (n > 1) rs = choose_radices(n, dtype);
+    } else {
+        if (!two_pass_split(n, dtype, &m, &k)) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no split");
+        rs = choose_radices(m, dtype);
+        auto r2 = choose_radices(k, dtype);
+        rs.insert(rs.end(), r2.begin(), r2.end());
+    }
+    if (split_m) *split_m = m;
+    *count = (int)rs.size();
+    if ((int)rs.size() > max_count) return fail(FFTC_ERR_INVALID_ARG, "max_count too small");
+    for (size_t i = 0; i < rs.size(); ++i) radices[i] = rs[i];
+    return FFTC_OK;
+}
+
+int64_t fftc_max_single_n(int dtype) { return max_single_n(dtype); }
+
+}  // extern "C"

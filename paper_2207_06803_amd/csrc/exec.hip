@@ -1,0 +1,233 @@
+// Kernel launches for single-kernel and two-pass plans.
+#include <algorithm>
+
+#include "plan.h"
+
+namespace fftc {
+
+extern "C" __shared__ __align__(16) unsigned char fftc_dyn_lds[];
+
+// ---------------------------------------------------------------------------
+// Runtime-length single kernel: one workgroup owns d.t transforms.
+// ---------------------------------------------------------------------------
+template <typename Real, bool INV>
+__global__ void __launch_bounds__(1024)
+stockham_generic(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __restrict__ tw,
+                 int64_t batch, GenDesc d) {
+    using C = cplx<Real>;
+    C* lds = reinterpret_cast<C*>(fftc_dyn_lds);
+    const int tr = (int)threadIdx.x / d.tpt;
+    const int t = (int)threadIdx.x - tr * d.tpt;
+    const int64_t b = (int64_t)blockIdx.x * d.t + tr;
+    const bool valid = b < batch;
+    const int64_t off = (valid ? b : 0) * (int64_t)d.n;
+    if (d.nst == 0) {  // N = 1: DFT_1 is the identity
+        if (valid && t == 0) out[off] = in[off];
+        return;
+    }
+    gen_transform<INV>(in + off, out + off, lds + tr * lds_len(d.n), tw, d, t, valid);
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass plan for N = M K (Eq. 2):
+//   pass 1: for each column i < K, DFT_M of x[j K + i] (j < M), i.e.
+//           (I_K (x) DFT_M) Pi^N_K, then the twiddle D^N_M: element (i, p)
+//           is scaled by w_N^{i p} and written to row i: z[i M + p].
+//   pass 2: for each p < M, DFT_K of z[i M + p] (i < K), written to
+//           y[q M + p] (q < K): (DFT_K (x) I_M).
+// A workgroup owns `tc` adjacent columns so every global access touches
+// tc * sizeof(complex) contiguous bytes; the column tile is staged in LDS.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int udiv(int a, uint32_t mul, int d) {
+    return d == 1 ? a : (int)__umulhi((uint32_t)a, mul);
+}
+
+template <typename Real, bool INV, int PASS>
+__global__ void __launch_bounds__(1024)
+four_step_pass(const cplx<Real>* src, cplx<Real>* dst, const cplx<Real>* __restrict__ tw,
+               const cplx<Real>* __restrict__ twn, GenDesc d, int64_t n, int ncols, int tc,
+               uint32_t len_mul) {
+    using C = cplx<Real>;
+    C* lds = reinterpret_cast<C*>(fftc_dyn_lds);
+    const int len = d.n;             // transform length of this pass
+    const int ldl = lds_len(len);
+    const int col0 = (int)blockIdx.x * tc;
+    const int cols = min(tc, ncols - col0);
+    const int64_t base = (int64_t)blockIdx.y * n;
+    const int nthr = (int)blockDim.x;
+    const int tot = tc * len;
+    // stride between successive elements of one column in src: pass 1 reads
+    // x[j K + i] (stride K = ncols), pass 2 reads z[i M + p] (stride M = ncols)
+    for (int l = (int)threadIdx.x; l < tot; l += nthr) {
+        const int c = l % tc, j = l / tc;
+        C v = mk((Real)0, (Real)0);
+        if (c < cols) {
+            v = src[base + (int64_t)j * ncols + col0 + c];
+            if (PASS == 1 && INV) v = cconj(v);
+        }
+        lds[c * ldl + lds_pad(j)] = v;
+    }
+    __syncthreads();
+    const int tr = (int)threadIdx.x / d.tpt;
+    const int t = (int)threadIdx.x - tr * d.tpt;
+    gen_transform<false>((const C*)nullptr, (C*)nullptr, lds + tr * ldl, tw, d, t, true, false, false);
+    if (PASS == 1) {
+        // row-major store z[(col0 + c) M + p] * w_N^{(col0 + c) p}; (col0+c) p < N
+        for (int l = (int)threadIdx.x; l < tot; l += nthr) {
+            const int c = udiv(l, len_mul, len);
+            const int p = l - c * len;
+            if (c < cols) {
+                const int i = col0 + c;
+                dst[base + (int64_t)i * len + p] = cmul(lds[c * ldl + lds_pad(p)], twn[(int64_t)i * p]);
+            }
+        }
+    } else {
+        // y[q M + col0 + c]
+        for (int l = (int)threadIdx.x; l < tot; l += nthr) {
+            const int c = l % tc, q = l / tc;
+            if (c < cols) {
+                C v = lds[c * ldl + lds_pad(q)];
+                dst[base + (int64_t)q * ncols + col0 + c] = INV ? cconj(v) : v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+void fill_gen_desc(int64_t n, const std::vector<int>& rs, int tpt, int t, int64_t twbase, GenDesc* d) {
+    *d = GenDesc{};
+    d->n = (int)n;
+    d->nst = (int)rs.size();
+    d->tpt = tpt;
+    d->t = t;
+    int64_t ns = 1, off = twbase;
+    for (size_t q = 0; q < rs.size(); ++q) {
+        StageRt& s = d->st[q];
+        s.r = rs[q];
+        s.ns = (int)ns;
+        s.twoff = (int)off;
+        s.ns_mul = ns > 1 ? (uint32_t)(((uint64_t(1) << 32) + ns - 1) / ns) : 0u;
+        off += (rs[q] - 1) * ns;
+        ns *= rs[q];
+    }
+}
+
+static uint32_t mul_for(int d) { return d > 1 ? (uint32_t)(((uint64_t(1) << 32) + d - 1) / d) : 0u; }
+
+template <typename Real>
+static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
+    using C = cplx<Real>;
+    const C* tin = static_cast<const C*>(in);
+    C* tout = static_cast<C*>(out);
+    const C* tw = static_cast<const C*>(p->tw);
+    int64_t batch = p->batch;
+    const bool inv = p->direction == FFTC_INVERSE;
+    if (p->spec) {
+        const int64_t groups = (batch + p->spec->t - 1) / p->spec->t;
+        void* args[] = {(void*)&tin, (void*)&tout, (void*)&tw, (void*)&batch};
+        hipError_t e = hipLaunchKernel(inv ? p->spec->inv : p->spec->fwd, dim3((unsigned)groups),
+                                       dim3(p->spec->tpt * p->spec->t), args, 0, s);
+        if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(stockham_spec)");
+    } else {
+        const int64_t groups = (batch + p->t - 1) / p->t;
+        if (inv)
+            hipLaunchKernelGGL((stockham_generic<Real, true>), dim3((unsigned)groups), dim3(p->tpt * p->t),
+                               p->lds_bytes, s, tin, tout, tw, batch, p->gdesc);
+        else
+            hipLaunchKernelGGL((stockham_generic<Real, false>), dim3((unsigned)groups), dim3(p->tpt * p->t),
+                               p->lds_bytes, s, tin, tout, tw, batch, p->gdesc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail_hip(e, "launch(stockham_generic)");
+    }
+    return FFTC_OK;
+}
+
+fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
+    return p->dtype == FFTC_C128 ? launch_single_t<double>(p, in, out, s)
+                                 : launch_single_t<float>(p, in, out, s);
+}
+
+// Columns per workgroup in a two-pass plan: 128 contiguous bytes per access.
+int two_pass_cols(int dtype) { return dtype == FFTC_C128 ? 8 : 16; }
+
+template <typename Real, bool INV>
+static fftc_status launch_two_pass_chunk(const fftc_plan_s* p, const cplx<Real>* tin, cplx<Real>* mid,
+                                         cplx<Real>* tout, const cplx<Real>* tw, const cplx<Real>* twn,
+                                         int tc, size_t csz, int64_t nb, hipStream_t s);
+
+template <typename Real, bool INV>
+static fftc_status launch_two_pass_t(const fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
+    using C = cplx<Real>;
+    const C* tin = static_cast<const C*>(in);
+    C* tout = static_cast<C*>(out);
+    const C* tw = static_cast<const C*>(p->tw);
+    const C* twn = tw + p->twn_off;
+    // the intermediate goes through `out` unless the call is in place
+    C* mid = (in == out) ? static_cast<C*>(p->scratch) : tout;
+    const int tc = two_pass_cols(p->dtype);
+    const size_t csz = sizeof(C);
+    // grid.y carries the transform index; split very large batches
+    constexpr int64_t kMaxY = 65535;
+    for (int64_t b0 = 0; b0 < p->batch; b0 += kMaxY) {
+        const int64_t nb = std::min<int64_t>(kMaxY, p->batch - b0);
+        const int64_t o = b0 * p->n;
+        fftc_status st = launch_two_pass_chunk<Real, INV>(p, tin + o, mid + o, tout + o, tw, twn, tc, csz, nb, s);
+        if (st != FFTC_OK) return st;
+    }
+    return FFTC_OK;
+}
+
+template <typename Real, bool INV>
+static fftc_status launch_two_pass_chunk(const fftc_plan_s* p, const cplx<Real>* tin, cplx<Real>* mid,
+                                         cplx<Real>* tout, const cplx<Real>* tw, const cplx<Real>* twn,
+                                         int tc, size_t csz, int64_t nb, hipStream_t s) {
+    using C = cplx<Real>;
+    {
+        const GenDesc& d = p->pass1;
+        dim3 grid((unsigned)((p->k + tc - 1) / tc), (unsigned)nb);
+        const size_t lds = (size_t)tc * lds_len(d.n) * csz;
+        hipLaunchKernelGGL((four_step_pass<Real, INV, 1>), grid, dim3(d.tpt * tc), lds, s, tin, mid, tw,
+                           twn, d, p->n, (int)p->k, tc, mul_for(d.n));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail_hip(e, "launch(four_step_pass 1)");
+    }
+    {
+        const GenDesc& d = p->pass2;
+        dim3 grid((unsigned)((p->m + tc - 1) / tc), (unsigned)nb);
+        const size_t lds = (size_t)tc * lds_len(d.n) * csz;
+        hipLaunchKernelGGL((four_step_pass<Real, INV, 2>), grid, dim3(d.tpt * tc), lds, s,
+                           (const C*)mid, tout, tw, twn, d, p->n, (int)p->m, tc, mul_for(d.n));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail_hip(e, "launch(four_step_pass 2)");
+    }
+    return FFTC_OK;
+}
+
+fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
+    const bool inv = p->direction == FFTC_INVERSE;
+    if (p->dtype == FFTC_C128)
+        return inv ? launch_two_pass_t<double, true>(p, in, out, s) : launch_two_pass_t<double, false>(p, in, out, s);
+    return inv ? launch_two_pass_t<float, true>(p, in, out, s) : launch_two_pass_t<float, false>(p, in, out, s);
+}
+
+// Allow the dynamic-LDS kernels to use up to the gfx950 per-group maximum.
+fftc_status enable_large_lds() {
+    static bool done = false;
+    if (done) return FFTC_OK;
+    const void* ks[] = {
+        (const void*)&stockham_generic<float, false>, (const void*)&stockham_generic<float, true>,
+        (const void*)&stockham_generic<double, false>, (const void*)&stockham_generic<double, true>,
+        (const void*)&four_step_pass<float, false, 1>, (const void*)&four_step_pass<float, false, 2>,
+        (const void*)&four_step_pass<float, true, 1>, (const void*)&four_step_pass<float, true, 2>,
+        (const void*)&four_step_pass<double, false, 1>, (const void*)&four_step_pass<double, false, 2>,
+        (const void*)&four_step_pass<double, true, 1>, (const void*)&four_step_pass<double, true, 2>,
+    };
+    for (const void* k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMaxPerGroup);
+        if (e != hipSuccess) return fail_hip(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
+    }
+    done = true;
+    return FFTC_OK;
+}
+
+}  // namespace fftc

@@ -1,0 +1,66 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fftc.h"
+#include "kconfig.h"
+
+namespace fftc {
+
+// ---- errors ---------------------------------------------------------------
+fftc_status fail(fftc_status s, const std::string& msg);
+fftc_status fail_hip(hipError_t e, const char* what);
+void clear_error();
+
+#define FFTC_HIP_TRY(call)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return ::fftc::fail_hip(e_, #call); \
+    } while (0)
+
+// ---- factorisation (planner.cpp, host only) -------------------------------
+bool is_7smooth(int64_t n);
+int64_t max_single_n(int dtype);
+int64_t max_total_n(int dtype);
+// Radix lists that multiply to n, in preference order (first = heuristic pick).
+std::vector<std::vector<int>> radix_candidates(int64_t n, int max_lists = 12);
+// Threads per transform and transforms per workgroup for a radix list.
+void launch_shape(int64_t n, const std::vector<int>& rs, int csize, int* tpt, int* t);
+// Two-pass split n = m k (pass 1: k columns of length m; pass 2: m of length k).
+bool two_pass_split(int64_t n, int dtype, int64_t* m, int64_t* k);
+// Tuning database: best radix list for (n, dtype), if recorded.
+bool tune_lookup(int64_t n, int dtype, std::vector<int>* rs);
+void tune_record(int64_t n, int dtype, const std::vector<int>& rs, double ms);
+
+// ---- kernels ----------------------------------------------------------------
+struct SpecEntry {
+    int dtype, n, nr;
+    int radices[kMaxStages];
+    int tpt, t;
+    const void* fwd;
+    const void* inv;
+};
+// Compiled specialisations (kernels_c64.hip / kernels_c128.hip).
+const SpecEntry* spec_table_c64(int* count);
+const SpecEntry* spec_table_c128(int* count);
+const SpecEntry* find_spec(int dtype, int64_t n, const std::vector<int>& rs);
+
+struct TwSegment {
+    int64_t off;    // first entry in the table
+    int64_t count;  // entries
+    int64_t ns;     // entry idx -> a = idx / ns + 1, b = idx % ns
+    int64_t len;    // value = w_len^{(a b) mod len}
+};
+// Fill table[seg.off + idx] = exp(-2 pi i ((a b) mod len) / len) in fp64,
+// stored as float2 (rounded to nearest) or double2.
+fftc_status make_twiddles(void* table, int dtype, const std::vector<TwSegment>& segs,
+                          hipStream_t stream);
+
+// Stage-twiddle segments for a Stockham radix list, appended at `base`.
+int64_t stage_segments(const std::vector<int>& rs, int64_t base, std::vector<TwSegment>* segs);
+
+}  // namespace fftc

@@ -1,0 +1,46 @@
+// Launch-shape rules shared by the host planner and the kernels.
+#pragma once
+
+namespace fftc {
+
+constexpr int kMaxStages = 8;
+constexpr int kMaxElemsPerThread = 16;   // register block per thread and stage
+constexpr int kWorkgroupTarget = 256;    // threads per workgroup when T > 1
+constexpr int kLdsBudgetPerGroup = 65536;
+constexpr int kLdsMaxPerGroup = 163840;  // gfx950: 160 KB per workgroup
+
+// LDS elements for one transform: one pad element every 16.
+__host__ __device__ constexpr int lds_len(int n) { return n + (n >> 4); }
+
+// Butterflies of radix r one thread holds at most in a stage.
+__host__ __device__ constexpr int nb_cap(int r) { return r >= kMaxElemsPerThread ? 1 : kMaxElemsPerThread / r; }
+
+// Threads needed per transform so every stage fits the register block.
+constexpr int required_tpt(int n, const int* rs, int nr) {
+    int m = 1;
+    for (int q = 0; q < nr; ++q) {
+        const int cap = nb_cap(rs[q]);
+        const int need = (n / rs[q] + cap - 1) / cap;
+        if (need > m) m = need;
+    }
+    return m;
+}
+
+// Round up to a power of two below one wave, to whole waves above.
+constexpr int round_tpt(int x) {
+    if (x >= 64) return (x + 63) / 64 * 64;
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Transforms per workgroup: fill kWorkgroupTarget threads within the LDS budget.
+constexpr int pick_t(int tpt, int n, int csize, bool multi_stage) {
+    if (tpt >= kWorkgroupTarget || (kWorkgroupTarget % tpt) != 0) return 1;
+    int t = kWorkgroupTarget / tpt;
+    const int per = multi_stage ? lds_len(n) * csize : 0;
+    while (t > 1 && t * per > kLdsBudgetPerGroup) t >>= 1;
+    return t;
+}
+
+}  // namespace fftc

@@ -1,0 +1,37 @@
+// The plan object behind fftc_plan_t.
+#pragma once
+#include <vector>
+
+#include "generic.h"
+#include "internal.h"
+
+struct fftc_plan_s {
+    int64_t n = 0, batch = 0;
+    int direction = FFTC_FORWARD, dtype = FFTC_C64;
+    int variant = FFTC_VARIANT_SINGLE_GENERIC;
+    int device = 0;
+    std::vector<int> radices;       // single kernel: the Stockham list
+    // single-kernel launch
+    const fftc::SpecEntry* spec = nullptr;
+    fftc::GenDesc gdesc{};
+    int tpt = 0, t = 0;
+    size_t lds_bytes = 0;
+    void* tw = nullptr;             // device twiddle table
+    size_t tw_bytes = 0;
+    // two-pass (Eq. 2 four-step): n = m k
+    int64_t m = 0, k = 0;
+    fftc::GenDesc pass1{}, pass2{};  // length m (k columns), length k (m columns)
+    std::vector<int> r1, r2;
+    int64_t tw1_off = 0, tw2_off = 0, twn_off = 0;  // table offsets (elements)
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+namespace fftc {
+
+fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, hipStream_t s);
+fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, hipStream_t s);
+// Fill a runtime descriptor for a radix list (twoff relative to twbase).
+void fill_gen_desc(int64_t n, const std::vector<int>& rs, int tpt, int t, int64_t twbase, GenDesc* d);
+
+}  // namespace fftc

@@ -1,0 +1,132 @@
+// Single-kernel Stockham FFT: one workgroup owns T whole transforms.
+//
+// The factorisation is DFT_N = S_t ... S_1 with, for stage q of radix R after
+// Ns = R_1 ... R_{q-1} (Eq. 2 applied recursively, in Stockham order):
+//   for j < N/R, k = j mod Ns:
+//     v_r = x[j + r N/R] * w_{Ns R}^{r k}            (twiddle diagonal)
+//     v   = DFT_R v                                  (DFT_R (x) I_{N/R})
+//     y[(j div Ns) Ns R + r Ns + k] = v_r            (stride permutation)
+// Stage 1 reads HBM directly (unit stride in j), the last stage (Ns R = N)
+// writes y[j + r N/R] to HBM in natural order, and the stages in between
+// exchange through LDS.  The LDS index is padded by one element every 16 so
+// that the stride-R writes of the early stages spread over the banks.
+#pragma once
+#include <stdint.h>
+
+#include "codelets.h"
+#include "kconfig.h"
+
+namespace fftc {
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+// Transform data is streamed exactly once in and once out: nontemporal
+// vector accesses (one dwordx2 / dwordx4 per element) keep it from displacing
+// the twiddle tables in the caches.
+template <bool INV, typename C> __device__ __forceinline__ C ld_in(const C* p) {
+    using V = typename vec_of<C>::type;
+    const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+    C v = mk(t.x, t.y);
+    return INV ? cconj(v) : v;
+}
+template <bool INV, typename C> __device__ __forceinline__ void st_out(C* p, C v) {
+    using V = typename vec_of<C>::type;
+    if (INV) v = cconj(v);
+    V t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<V*>(p));
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time specialised kernel: N, radix sequence, threads per transform
+// (TPT) and transforms per workgroup (T) are template parameters, so every
+// index division folds to shifts / multiplies.
+// ---------------------------------------------------------------------------
+template <typename Real, int N_, int TPT_, int T_, bool INV_>
+struct SpecCfg {
+    using C = cplx<Real>;
+    static constexpr int N = N_, TPT = TPT_, T = T_;
+    static constexpr bool INV = INV_;
+};
+
+template <class K, int R, int NS, int TWOFF, bool FIRST, bool LAST>
+__device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K::C* gout,
+                                           typename K::C* lds,
+                                           const typename K::C* __restrict__ tw, int t, bool valid) {
+    using C = typename K::C;
+    constexpr int N = K::N, TPT = K::TPT;
+    constexpr int NR = N / R;
+    constexpr int NB = (NR + TPT - 1) / TPT;
+    constexpr bool EVEN = (NR % TPT) == 0;
+    C v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = t + i * TPT;
+        if (EVEN || j < NR) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (FIRST) {
+                    // unconditional: the caller clamps gin to a real transform
+                    // for out-of-range groups, whose results are never stored
+                    v[i][r] = ld_in<K::INV>(gin + j + r * NR);
+                } else {
+                    v[i][r] = lds[lds_pad(j + r * NR)];
+                }
+            }
+            if constexpr (NS > 1) {
+                const int k = j % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[TWOFF + (r - 1) * NS + k]);
+            }
+            Codelet<R, C>::run(v[i]);
+        }
+    }
+    if constexpr (!FIRST) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = t + i * TPT;
+        if (EVEN || j < NR) {
+            const int k = j % NS;
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (LAST) {
+                    if (valid) st_out<K::INV>(gout + base + r * NS, v[i][r]);
+                } else {
+                    lds[lds_pad(base + r * NS)] = v[i][r];
+                }
+            }
+        }
+    }
+    if constexpr (!LAST) __syncthreads();
+}
+
+template <class K, int NS, int TWOFF, bool FIRST, int R, int... Rest>
+__device__ __forceinline__ void spec_stages(const typename K::C* gin, typename K::C* gout,
+                                            typename K::C* lds,
+                                            const typename K::C* __restrict__ tw, int t, bool valid) {
+    constexpr bool LAST = sizeof...(Rest) == 0;
+    spec_stage<K, R, NS, TWOFF, FIRST, LAST>(gin, gout, lds, tw, t, valid);
+    if constexpr (!LAST)
+        spec_stages<K, NS * R, TWOFF + (R - 1) * NS, false, Rest...>(gin, gout, lds, tw, t, valid);
+}
+
+template <class K, int... Rs>
+__global__ void __launch_bounds__(K::TPT * K::T)
+stockham_spec(const typename K::C* in, typename K::C* out,
+              const typename K::C* __restrict__ tw, int64_t batch) {
+    using C = typename K::C;
+    constexpr int N = K::N, TPT = K::TPT, T = K::T;
+    constexpr bool MULTI = sizeof...(Rs) > 1;
+    constexpr int LDSN = MULTI ? lds_len(N) : 1;
+    __shared__ C lds[T * LDSN];
+    const int tr = (T == 1) ? 0 : (int)(threadIdx.x / TPT);
+    const int t = (T == 1) ? (int)threadIdx.x : (int)(threadIdx.x % TPT);
+    const int64_t b = (int64_t)blockIdx.x * T + tr;
+    const bool valid = b < batch;
+    const int64_t off = (valid ? b : 0) * (int64_t)N;
+    spec_stages<K, 1, 0, true, Rs...>(in + off, out + off, lds + tr * LDSN, tw, t, valid);
+}
+
+}  // namespace fftc

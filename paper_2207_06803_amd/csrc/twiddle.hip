@@ -1,0 +1,67 @@
+// Twiddle tables, generated on the GPU in fp64.
+//
+// Each segment describes entries value(idx) = w_L^{(a b) mod L} with
+// a = idx / ns + 1, b = idx mod ns and w_L = exp(-2 pi i / L).  For a
+// Stockham stage of radix R after Ns (the twiddle diagonal of Eq. 2 at
+// length Ns R) this is the [r - 1][k] table of w_{Ns R}^{r k}; with ns = L
+// it is the plain table w_L^b used by the two-pass plans.  The exponent is
+// reduced exactly in integers and the angle is taken in (-pi, pi] before
+// sincospi, so the quarter turns come out exact.  complex64 plans round
+// the fp64 value to nearest fp32.
+#include "internal.h"
+
+namespace fftc {
+
+struct TwSegDev {
+    int64_t off, count, ns, len;
+};
+
+template <typename C>
+__global__ void twiddle_kernel(C* table, const TwSegDev* __restrict__ segs) {
+    const TwSegDev s = segs[blockIdx.y];
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < s.count;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = idx / s.ns + 1, b = idx % s.ns;
+        int64_t m = (a * b) % s.len;
+        if (2 * m > s.len) m -= s.len;  // angle in (-pi, pi]
+        double sn, cs;
+        // w = exp(-2 pi i m / L) = cos(2 pi m/L) - i sin(2 pi m/L)
+        sincospi(2.0 * (double)m / (double)s.len, &sn, &cs);
+        C v;
+        v.x = cs;
+        v.y = -sn;
+        table[s.off + idx] = v;
+    }
+}
+
+fftc_status make_twiddles(void* table, int dtype, const std::vector<TwSegment>& segs,
+                          hipStream_t stream) {
+    if (segs.empty()) return FFTC_OK;
+    std::vector<TwSegDev> h(segs.size());
+    int64_t maxc = 1;
+    for (size_t i = 0; i < segs.size(); ++i) {
+        h[i] = {segs[i].off, segs[i].count, segs[i].ns, segs[i].len};
+        maxc = std::max<int64_t>(maxc, segs[i].count);
+    }
+    if (segs.size() > 65535) return fail(FFTC_ERR_INTERNAL, "too many twiddle segments");
+    TwSegDev* d = nullptr;
+    FFTC_HIP_TRY(hipMalloc(&d, sizeof(TwSegDev) * h.size()));
+    hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(TwSegDev) * h.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) {
+        const int block = 256;
+        const int64_t gx = std::min<int64_t>((maxc + block - 1) / block, 4096);
+        dim3 grid((unsigned)gx, (unsigned)h.size());
+        if (dtype == FFTC_C128)
+            hipLaunchKernelGGL(twiddle_kernel<double2>, grid, dim3(block), 0, stream, (double2*)table, d);
+        else
+            hipLaunchKernelGGL(twiddle_kernel<float2>, grid, dim3(block), 0, stream, (float2*)table, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    hipError_t e2 = hipFree(d);
+    if (e != hipSuccess) return fail_hip(e, "twiddle generation");
+    if (e2 != hipSuccess) return fail_hip(e2, "hipFree(twiddle segments)");
+    return FFTC_OK;
+}
+
+}  // namespace fftc

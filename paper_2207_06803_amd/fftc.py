@@ -1,0 +1,195 @@
+"""Python binding of the fftc C ABI (include/fftc.h).
+
+Argument marshalling only: every transform runs in the HIP kernels of
+libfftc.so.  PyTorch is used by callers for device memory and streams; this
+module accepts anything with a `data_ptr()` (a torch tensor) or a raw integer
+device address.  If libfftc.so is missing the import fails loudly -- there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfftc.so")
+
+FORWARD = -1
+INVERSE = +1
+C64 = 0
+C128 = 1
+DTYPES = {"c64": C64, "complex64": C64, C64: C64, "c128": C128, "complex128": C128, C128: C128}
+
+VARIANT_NAMES = {0: "single_specialised", 1: "single_generic", 2: "two_pass"}
+
+STATUS = {0: "FFTC_OK", 1: "FFTC_ERR_INVALID_ARG", 2: "FFTC_ERR_UNSUPPORTED_SIZE",
+          3: "FFTC_ERR_OUT_OF_MEMORY", 4: "FFTC_ERR_TOO_LARGE", 5: "FFTC_ERR_HIP",
+          6: "FFTC_ERR_SHUTDOWN", 7: "FFTC_ERR_INTERNAL"}
+
+
+class FFTCError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("batch", ctypes.c_int64), ("direction", ctypes.c_int),
+                ("dtype", ctypes.c_int), ("variant", ctypes.c_int), ("nradices", ctypes.c_int),
+                ("radices", ctypes.c_int * 16), ("threads_per_transform", ctypes.c_int),
+                ("transforms_per_group", ctypes.c_int), ("split_m", ctypes.c_int64),
+                ("split_k", ctypes.c_int64), ("twiddle_bytes", ctypes.c_size_t),
+                ("scratch_bytes", ctypes.c_size_t)]
+
+
+_i64, _int, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+_SIGNATURES = {
+    "fftc_plan": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(_vp)]),
+    "fftc_plan_radices": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(_int), _int, ctypes.POINTER(_vp)]),
+    "fftc_execute": (_int, [_vp, _vp, _vp, _vp]),
+    "fftc_destroy_plan": (_int, [_vp]),
+    "fftc_plan_describe": (_int, [_vp, ctypes.POINTER(PlanDesc)]),
+    "fftc_factorize": (_int, [_i64, _int, ctypes.POINTER(_int), _int, ctypes.POINTER(_int),
+                              ctypes.POINTER(_i64)]),
+    "fftc_max_single_n": (_i64, [_int]),
+    "fftc_status_string": (ctypes.c_char_p, [_int]),
+    "fftc_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _load() -> ctypes.CDLL:
+    # PyTorch-ROCm carries its own HIP runtime (libamdhip64.so.7).  Import it
+    # first so libfftc.so binds to that same runtime (same soname) and the
+    # process holds one HIP runtime shared by torch's allocations/streams and
+    # fftc's launches.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def register(name: str, restype, argtypes) -> None:
+    """Declare the signature of a further C entry point of the library."""
+    fn = getattr(lib, name)
+    fn.restype = restype
+    fn.argtypes = argtypes
+
+
+def last_error() -> str:
+    return (lib.fftc_last_error() or b"").decode()
+
+
+def check(status: int, where: str) -> None:
+    if status != 0:
+        raise FFTCError(status, where, last_error())
+
+
+def ptr(x) -> int:
+    """Device address of a tensor (data_ptr()) or an integer address."""
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def stream_handle(stream) -> int:
+    """hipStream_t of a torch stream, an int handle, or torch's current stream."""
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def dtype_code(dtype) -> int:
+    if dtype in DTYPES:
+        return DTYPES[dtype]
+    s = str(dtype).replace("torch.", "")
+    if s in DTYPES:
+        return DTYPES[s]
+    raise ValueError(f"unsupported dtype {dtype!r}")
+
+
+class Plan:
+    """Owns an fftc_plan_t; destroyed by close() or garbage collection."""
+
+    def __init__(self, n: int, batch: int, direction: int = FORWARD, dtype="c64", radices=None):
+        h = _vp()
+        code = dtype_code(dtype)
+        if radices is None:
+            check(lib.fftc_plan(n, batch, direction, code, ctypes.byref(h)), "fftc_plan")
+        else:
+            arr = (_int * max(1, len(radices)))(*radices)
+            check(lib.fftc_plan_radices(n, batch, direction, code, arr, len(radices), ctypes.byref(h)),
+                  "fftc_plan_radices")
+        self._h = h
+        self.n, self.batch, self.direction, self.dtype = n, batch, direction, code
+
+    @property
+    def handle(self) -> int:
+        return self._h.value or 0
+
+    def execute(self, x, y, stream=None) -> None:
+        """Enqueue y = DFT(x) on the stream (default: torch's current stream)."""
+        check(lib.fftc_execute(self._h, ptr(x), ptr(y), stream_handle(stream)), "fftc_execute")
+
+    def describe(self) -> dict:
+        d = PlanDesc()
+        check(lib.fftc_plan_describe(self._h, ctypes.byref(d)), "fftc_plan_describe")
+        return {"n": d.n, "batch": d.batch, "direction": d.direction, "dtype": d.dtype,
+                "variant": VARIANT_NAMES.get(d.variant, d.variant),
+                "radices": list(d.radices[:d.nradices]),
+                "threads_per_transform": d.threads_per_transform,
+                "transforms_per_group": d.transforms_per_group,
+                "split_m": d.split_m, "split_k": d.split_k,
+                "twiddle_bytes": d.twiddle_bytes, "scratch_bytes": d.scratch_bytes}
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            check(lib.fftc_destroy_plan(self._h), "fftc_destroy_plan")
+        self._h = _vp()
+
+    def __del__(self):
+        try:
+            if self._h is not None and self._h.value:
+                lib.fftc_destroy_plan(self._h)
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def factorize(n: int, dtype="c64"):
+    """Radix list the planner picks for n (host only), and the two-pass split m (0 if none)."""
+    arr = (_int * 32)()
+    cnt = _int()
+    m = _i64()
+    check(lib.fftc_factorize(n, dtype_code(dtype), arr, 32, ctypes.byref(cnt), ctypes.byref(m)),
+          "fftc_factorize")
+    return list(arr[:cnt.value]), m.value
+
+
+def max_single_n(dtype="c64") -> int:
+    return int(lib.fftc_max_single_n(dtype_code(dtype)))
+
+
+def status_string(code: int) -> str:
+    return lib.fftc_status_string(code).decode()

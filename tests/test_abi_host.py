@@ -1,0 +1,102 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and
+its host-only planner emits factorisations that multiply to DFT_N."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import factor_algebra as F
+from paper_2207_06803_amd import fftc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(fftc_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("fftc_plan", "fftc_execute", "fftc_destroy_plan", "fftc_status_string",
+                 "fftc_last_error", "fftc_factorize"):
+        assert must in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_library_exports_symbol(name):
+    lib = ctypes.CDLL(fftc.LIB_PATH)
+    assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for code, text in fftc.STATUS.items():
+        assert fftc.status_string(code) == text
+
+
+SIZES = sorted({1 << k for k in range(1, 15)} | {3 << k for k in range(0, 10)} |
+               {5 << k for k in range(0, 10)} | {7 << k for k in range(0, 10)} | {9, 15, 21, 35, 105, 225})
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_factorize_products(dtype):
+    for n in SIZES:
+        if n > fftc.max_single_n(dtype):
+            continue
+        rs, m = fftc.factorize(n, dtype)
+        assert m == 0
+        assert int(np.prod(rs)) == n, (n, rs)
+        assert all(r in (2, 3, 4, 5, 7, 8, 16) for r in rs)
+
+
+@pytest.mark.parametrize("n", [n for n in SIZES if 1 < n <= 256])
+def test_planner_lists_multiply_to_dft(n):
+    rs, _ = fftc.factorize(n, "c64")
+    got = F.stockham_product(n, rs)
+    assert np.abs(got - F.dft_matrix(n)).max() < 1e-11, (n, rs)
+
+
+def test_two_pass_split():
+    for n in (32768, 65536, 1 << 18, 1 << 20, 3 * 16384, 7 * 4096 * 2):
+        rs, m = fftc.factorize(n, "c64")
+        assert m > 0 and n % m == 0 and m <= 1024 and n // m <= 1024, (n, m)
+        assert int(np.prod(rs)) == n
+    rs, m = fftc.factorize(16384, "c128")
+    assert m > 0
+
+
+@pytest.mark.parametrize("n", [0, -4, 11, 13 * 4, (1 << 20) * 2, 3 ** 13])
+def test_unsupported_sizes_rejected_on_host(n):
+    with pytest.raises(fftc.FFTCError) as e:
+        fftc.Plan(n, 4)
+    assert e.value.status == 2
+    with pytest.raises(fftc.FFTCError):
+        fftc.factorize(n)
+
+
+def test_bad_arguments_rejected_on_host():
+    with pytest.raises(fftc.FFTCError) as e:
+        fftc.Plan(64, 0)
+    assert e.value.status == 1 and "batch" in fftc.last_error()
+    with pytest.raises(fftc.FFTCError) as e:
+        fftc.Plan(64, 1, direction=0)
+    assert e.value.status == 1
+    h = ctypes.c_void_p()
+    assert fftc.lib.fftc_plan(64, 1, -1, 7, ctypes.byref(h)) == 1 and not h.value
+    assert fftc.lib.fftc_plan(64, 1, -1, 0, None) == 1
+    with pytest.raises(fftc.FFTCError) as e:
+        fftc.Plan(64, 1, radices=[4, 4, 2])
+    assert e.value.status == 1
+    with pytest.raises(fftc.FFTCError) as e:
+        fftc.Plan(64, 1, radices=[64])
+    assert e.value.status == 1
+    # NULL plan
+    assert fftc.lib.fftc_execute(None, None, None, None) == 1
+    assert fftc.lib.fftc_destroy_plan(None) == 0

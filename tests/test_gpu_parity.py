@@ -1,0 +1,171 @@
+"""GPU path against the FP64 oracle through the C ABI (single-kernel plans)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import np_dtype, rel_l2, run_plan, say, tol_for
+from paper_2207_06803_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2207_06803_amd import fftc  # noqa: E402
+
+FWD, INV = fftc.FORWARD, fftc.INVERSE
+
+
+def check(n, batch, direction, dtype, radices=None, seed=0, inplace=False, x=None):
+    say(f"case n={n} batch={batch} dir={direction} dtype={dtype} radices={radices} inplace={inplace}")
+    if x is None:
+        x = synth.uniform_complex(synth.rng(90, seed, n % 1000), (batch, n), np_dtype(dtype))
+    with fftc.Plan(n, batch, direction, dtype, radices=radices) as p:
+        y = run_plan(p, x, inplace=inplace)
+        desc = p.describe()
+    ref = oracle.dft(x, direction)
+    err = rel_l2(y, ref)
+    assert err.max() <= tol_for(n, dtype), (n, dtype, direction, radices, err.max(), desc)
+    return err, desc
+
+
+def test_config1_n64_batch1024_full():
+    # forward complex64, N = 64, 1024 transforms, uniform[-1,1): every output
+    x = synth.uniform_complex(synth.rng(0), (1024, 64), np.complex64)
+    err, desc = check(64, 1024, FWD, "c64", x=x)
+    assert err.max() <= 6e-6
+    say("config1 max rel L2", err.max(), desc["variant"], desc["radices"])
+
+
+SPEC_C64 = [(8, [8]), (16, [16]), (32, [2, 16]), (32, [16, 2]), (32, [4, 8]), (32, [8, 4]),
+            (64, [4, 16]), (64, [16, 4]), (64, [8, 8]), (128, [8, 16]), (128, [16, 8]),
+            (256, [16, 16]), (256, [4, 4, 16]), (512, [8, 8, 8]), (512, [2, 16, 16]),
+            (512, [16, 16, 2]), (1024, [4, 16, 16]), (1024, [16, 16, 4]), (1024, [16, 4, 16]),
+            (1024, [8, 8, 16]), (2048, [8, 16, 16]), (2048, [16, 16, 8]), (4096, [16, 16, 16]),
+            (4096, [8, 8, 8, 8]), (4096, [4, 16, 4, 16]), (8192, [2, 16, 16, 16]),
+            (8192, [16, 16, 16, 2]), (8192, [8, 16, 8, 8]), (16384, [4, 16, 16, 16]),
+            (16384, [16, 16, 16, 4])]
+SPEC_C128 = [(8, [8]), (16, [16]), (32, [2, 16]), (32, [8, 4]), (64, [4, 16]), (64, [8, 8]),
+             (128, [8, 16]), (128, [16, 8]), (256, [16, 16]), (256, [4, 4, 16]), (512, [8, 8, 8]),
+             (512, [2, 16, 16]), (1024, [4, 16, 16]), (1024, [16, 16, 4]), (1024, [8, 8, 16]),
+             (2048, [8, 16, 16]), (2048, [16, 16, 8]), (4096, [16, 16, 16]), (4096, [8, 8, 8, 8]),
+             (8192, [2, 16, 16, 16]), (8192, [16, 16, 16, 2])]
+
+
+def _ragged_batch(n):
+    # several workgroups and a partial last one
+    per = max(1, 256 // max(1, n // 16))
+    b = 3 * per + 1
+    while b * n > (1 << 18) and b > 3:
+        b = b // 2 + 1
+    return b
+
+
+@pytest.mark.parametrize("n,rs", SPEC_C64, ids=lambda v: str(v))
+def test_specialised_c64(n, rs):
+    for d in (FWD, INV):
+        _, desc = check(n, _ragged_batch(n), d, "c64", radices=rs)
+        assert desc["variant"] == "single_specialised", desc
+
+
+@pytest.mark.parametrize("n,rs", SPEC_C128, ids=lambda v: str(v))
+def test_specialised_c128(n, rs):
+    for d in (FWD, INV):
+        _, desc = check(n, _ragged_batch(n), d, "c128", radices=rs)
+        assert desc["variant"] == "single_specialised", desc
+
+
+GENERIC_C64 = [(12, [4, 3]), (12, [3, 4]), (3072, [3, 4, 16, 16]), (3584, [7, 8, 8, 8]),
+               (2560, [5, 8, 4, 16]), (64, [2, 2, 2, 2, 2, 2]), (4096, [4, 4, 4, 4, 4, 4]),
+               (1024, [2, 8, 4, 16]), (16384, [2, 8, 16, 4, 16]), (105, [3, 5, 7]),
+               (225, [3, 3, 5, 5]), (343, [7, 7, 7]), (10, [2, 5]), (14, [7, 2])]
+
+
+@pytest.mark.parametrize("n,rs", GENERIC_C64, ids=lambda v: str(v))
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_generic_explicit_lists(n, rs, dtype):
+    if n > fftc.max_single_n(dtype):
+        pytest.skip("two-pass length for this dtype")
+    for d in (FWD, INV):
+        _, desc = check(n, _ragged_batch(n), d, dtype, radices=rs)
+        assert desc["radices"] == rs
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_mixed_size_set_default_plans(dtype):
+    for n in synth.mixed_size_set() + [1, 2, 3, 4, 5, 6, 7, 9, 15, 21, 35, 49, 125, 6561 // 27 * 3]:
+        for d in (FWD, INV):
+            check(n, _ragged_batch(n), d, dtype)
+
+
+@pytest.mark.parametrize("n", [256, 1024, 4096])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_config2_sizes_full_oracle(n, dtype):
+    # batch scaled down so the O(N^2) oracle finishes in seconds
+    batch = (1 << 17) // n + 3
+    for d in (FWD, INV):
+        err, desc = check(n, batch, d, dtype, seed=2)
+        say(f"config2 n={n} {dtype} dir={d} max rel L2 {err.max():.3e} {desc['variant']} {desc['radices']}")
+
+
+@pytest.mark.parametrize("n", [256, 1024, 4096])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_config2_full_size_sampled(n, dtype):
+    # the benchmarked shape: 2^24 elements per run; sampled transforms against
+    # the oracle, Parseval on every transform
+    batch = (1 << 24) // n
+    g = synth.rng(1, n, 0 if dtype == "c64" else 1)
+    x = synth.uniform_complex(g, (batch, n), np_dtype(dtype))
+    rows = np.unique(np.r_[0, batch - 1, g.integers(0, batch, 6)])
+    for d in (FWD, INV):
+        say(f"config2 full n={n} batch={batch} {dtype} dir={d}")
+        with fftc.Plan(n, batch, d, dtype) as p:
+            y = run_plan(p, x)
+        err = rel_l2(y[rows], oracle.dft(x[rows], d))
+        assert err.max() <= tol_for(n, dtype), err.max()
+        ex = (np.abs(x.astype(np.complex128)) ** 2).sum(axis=1) * n
+        ey = (np.abs(y.astype(np.complex128)) ** 2).sum(axis=1)
+        rel = np.abs(ey - ex) / ex
+        assert rel.max() <= 2 * tol_for(n, dtype), rel.max()
+
+
+def test_inplace_single_kernel():
+    for n, dtype in ((1024, "c64"), (3584, "c64"), (4096, "c128"), (64, "c64")):
+        check(n, 37, FWD, dtype, inplace=True)
+        check(n, 37, INV, dtype, inplace=True)
+
+
+def test_round_trip_and_delta():
+    n, b = 4096, 8
+    g = synth.rng(91)
+    x = synth.uniform_complex(g, (b, n), np.complex64)
+    with fftc.Plan(n, b, FWD) as pf, fftc.Plan(n, b, INV) as pi:
+        y = run_plan(pf, x)
+        z = run_plan(pi, y)
+        assert rel_l2(z / n, x).max() <= 2 * tol_for(n, "c64")
+        d = np.zeros((b, n), np.complex64)
+        d[:, 0] = 1
+        yd = run_plan(pf, d)
+        assert np.abs(yd - 1).max() <= 1e-5
+
+
+def test_bitwise_deterministic():
+    n, b = 1024, 333
+    x = synth.uniform_complex(synth.rng(92), (b, n), np.complex64)
+    with fftc.Plan(n, b, FWD) as p:
+        y1 = run_plan(p, x)
+        y2 = run_plan(p, x)
+    assert np.array_equal(y1.view(np.uint32), y2.view(np.uint32))
+
+
+def test_misaligned_pointer_rejected():
+    x = torch.zeros(65, dtype=torch.complex64, device="cuda")
+    with fftc.Plan(64, 1, FWD, "c64") as p:
+        with pytest.raises(fftc.FFTCError) as e:
+            p.execute(x.data_ptr() + 4, x.data_ptr() + 8 * 0)
+        assert e.value.status == 1
+    xd = torch.zeros(65, dtype=torch.complex128, device="cuda")
+    with fftc.Plan(64, 1, FWD, "c128") as p:
+        with pytest.raises(fftc.FFTCError):
+            p.execute(xd.data_ptr() + 8, xd.data_ptr())

@@ -30,7 +30,7 @@ MUTANTS = {
 
 def _build(tmp_path, name, old, new):
     src = open(SRC).read()
-    assert src.count(old) == 1, name
+    assert src.count(old) >= 1, name
     path = tmp_path / f"{name}.c"
     path.write_text(src.replace(old, new))
     lib = tmp_path / f"lib{name}.so"
