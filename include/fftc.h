@@ -56,7 +56,8 @@ enum {
 enum {
     FFTC_VARIANT_SINGLE_SPECIALISED = 0, /* one kernel compiled for this N and radix list */
     FFTC_VARIANT_SINGLE_GENERIC = 1,     /* one kernel, runtime N and radix list */
-    FFTC_VARIANT_TWO_PASS = 2            /* Eq. 2 four-step in two kernels + scratch */
+    FFTC_VARIANT_TWO_PASS = 2,           /* Eq. 2 four-step in two kernels + scratch */
+    FFTC_VARIANT_MIXED_PERSISTENT = 3    /* mixed lengths, one persistent launch in a hipGraph */
 };
 
 typedef struct fftc_plan_s *fftc_plan_t;
@@ -105,6 +106,10 @@ typedef struct {
     int transforms_per_group;
     int64_t split_m, split_k;  /* two-pass: n = m k; else 0 */
     size_t twiddle_bytes, scratch_bytes;
+    /* mixed plans: transforms, total elements, distinct lengths, work items,
+     * persistent workgroups */
+    int64_t mixed_transforms, mixed_elements;
+    int mixed_classes, mixed_items, persistent_groups;
 } fftc_plan_desc;
 
 fftc_status fftc_plan_describe(fftc_plan_t plan, fftc_plan_desc *desc);
@@ -117,8 +122,58 @@ fftc_status fftc_plan_describe(fftc_plan_t plan, fftc_plan_desc *desc);
 fftc_status fftc_factorize(int64_t n, int dtype, int *radices, int max_count, int *count,
                            int64_t *split_m);
 
+/*
+ * Host-only: the candidate Stockham radix lists for single-kernel length n,
+ * in the planner's preference order (the autotuner times these).  List i is
+ * radices[i * 16 .. i * 16 + lens[i]); at most max_lists lists are written,
+ * *nlists is how many there are (up to 12).
+ */
+fftc_status fftc_candidates(int64_t n, int *radices, int *lens, int max_lists, int *nlists);
+
+/*
+ * Host-only: the radix lists compiled as specialised kernels for dtype.
+ * Entry i (0 <= i < fftc_compiled_count(dtype)) has length *n and list
+ * radices[0..*count); max_count is the capacity of radices (>= 8).
+ */
+int fftc_compiled_count(int dtype);
+fftc_status fftc_compiled_entry(int dtype, int i, int64_t *n, int *radices, int max_count, int *count);
+
 /* Host-only: largest n that runs as one kernel for dtype. */
 int64_t fftc_max_single_n(int dtype);
+
+/*
+ * Mixed-length plan: `count` transforms of lengths n[0..count), packed back to
+ * back in that order (transform i starts at element n[0] + ... + n[i-1]) in
+ * both in and out.  Every length must satisfy 1 <= n[i] <= 4096 with prime
+ * factors <= 7.  The uneven batch runs as one persistent launch: equal lengths
+ * form classes with their own radix list (tuning database or heuristic), work
+ * items are ordered longest first and pulled by the resident workgroups from
+ * an atomic counter.  The counter reset and the launch are recorded in a
+ * hipGraph at plan time; fftc_execute replays it on the caller's stream
+ * (updating the graph's pointer arguments when in/out change).  Executions of
+ * one mixed plan must not overlap (they share the work counter).
+ */
+fftc_status fftc_plan_mixed(const int64_t *n, int64_t count, int direction, int dtype,
+                            fftc_plan_t *plan_out);
+
+/*
+ * Autotuner.  Times every candidate Stockham radix list for single-kernel
+ * length n (batch transforms, forward, on an internal stream with scratch
+ * buffers it allocates and frees), keeps the fastest -- ties within 1% go to
+ * fewer stages, then to the larger leading radix -- and records it in the
+ * process's tuning database, which later plans for (n, dtype) use.  Returns
+ * the chosen list in radices[0..*count) and its mean time per launch in
+ * microseconds.  `reps` launches per timing (>= 1).  Synchronous.
+ */
+fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int *radices,
+                          int max_count, int *count, double *best_us);
+
+/* Tuning database persistence (text, one line per (arch, dtype, n)).  The
+ * database is also read once from the file named by FFTC_TUNE_DB, if set.
+ * fftc_tune_load merges the file's entries (*entries = lines accepted). */
+fftc_status fftc_tune_load(const char *path, int *entries);
+fftc_status fftc_tune_save(const char *path, int *entries);
+fftc_status fftc_tune_clear(void);
 
 /* Text of a status code (static storage). */
 const char *fftc_status_string(fftc_status s);

@@ -28,14 +28,16 @@ fftc_status enable_large_lds();
 int two_pass_cols(int dtype);
 
 const SpecEntry* find_spec(int dtype, int64_t n, const std::vector<int>& rs) {
-    int cnt = 0;
-    const SpecEntry* tab = dtype == FFTC_C128 ? spec_table_c128(&cnt) : spec_table_c64(&cnt);
-    for (int i = 0; i < cnt; ++i) {
-        const SpecEntry& e = tab[i];
-        if (e.n != n || e.nr != (int)rs.size()) continue;
-        bool same = true;
-        for (int q = 0; q < e.nr; ++q) same = same && e.radices[q] == rs[q];
-        if (same) return &e;
+    for (int part = 0; part < kSpecParts; ++part) {
+        int cnt = 0;
+        const SpecEntry* tab = spec_part(dtype, part, &cnt);
+        for (int i = 0; i < cnt; ++i) {
+            const SpecEntry& e = tab[i];
+            if (e.n != n || e.nr != (int)rs.size()) continue;
+            bool same = true;
+            for (int q = 0; q < e.nr; ++q) same = same && e.radices[q] == rs[q];
+            if (same) return &e;
+        }
     }
     return nullptr;
 }
@@ -54,12 +56,6 @@ static fftc_status check_radices(int64_t n, const std::vector<int>& rs) {
     return FFTC_OK;
 }
 
-static std::vector<int> choose_radices(int64_t n, int dtype) {
-    std::vector<int> rs;
-    if (tune_lookup(n, dtype, &rs)) return rs;
-    auto c = radix_candidates(n, 1);
-    return c.empty() ? rs : c[0];
-}
 
 // Shape a single-kernel transform of length n with list rs.
 static fftc_status shape_single(fftc_plan_s* p, const std::vector<int>& rs) {
@@ -226,6 +222,44 @@ fftc_status fftc_plan_radices(int64_t n, int64_t batch, int direction, int dtype
     }
 }
 
+fftc_status fftc_plan_mixed(const int64_t* n, int64_t count, int direction, int dtype, fftc_plan_t* plan_out) {
+    clear_error();
+    if (!plan_out) return fail(FFTC_ERR_INVALID_ARG, "plan_out is NULL");
+    *plan_out = nullptr;
+    if (!n || count < 1) return fail(FFTC_ERR_INVALID_ARG, "need count >= 1 lengths");
+    if (direction != FFTC_FORWARD && direction != FFTC_INVERSE)
+        return fail(FFTC_ERR_INVALID_ARG, "direction must be FFTC_FORWARD (-1) or FFTC_INVERSE (+1)");
+    if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
+    if (count > (int64_t(1) << 30)) return fail(FFTC_ERR_INVALID_ARG, "too many transforms");
+    for (int64_t i = 0; i < count; ++i)
+        if (n[i] < 1 || n[i] > kMixedMaxLen || !is_7smooth(n[i]))
+            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "mixed length n[" + std::to_string(i) + "] = " +
+                                                       std::to_string(n[i]) + " unsupported (1..4096, 7-smooth)");
+    try {
+        fftc_status st = enable_large_lds();
+        if (st != FFTC_OK) return st;
+        fftc_plan_s* p = new (std::nothrow) fftc_plan_s();
+        if (!p) return fail(FFTC_ERR_OUT_OF_MEMORY, "host allocation failed");
+        p->n = 0;
+        p->batch = count;
+        p->direction = direction;
+        p->dtype = dtype;
+        p->variant = FFTC_VARIANT_MIXED_PERSISTENT;
+        hipGetDevice(&p->device);
+        st = build_mixed(p, n, count);
+        if (st != FFTC_OK) {
+            std::string keep = t_last_error;
+            fftc_destroy_plan(p);
+            t_last_error = keep;
+            return st;
+        }
+        *plan_out = p;
+        return FFTC_OK;
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_plan_mixed");
+    }
+}
+
 fftc_status fftc_execute(fftc_plan_t p, const void* in, void* out, void* stream) {
     clear_error();
     if (!p) return fail(FFTC_ERR_INVALID_ARG, "plan is NULL");
@@ -234,6 +268,7 @@ fftc_status fftc_execute(fftc_plan_t p, const void* in, void* out, void* stream)
     if (((uintptr_t)in % align) || ((uintptr_t)out % align))
         return fail(FFTC_ERR_INVALID_ARG, "in/out not aligned to the complex element size");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->variant == FFTC_VARIANT_MIXED_PERSISTENT) return launch_mixed(p, in, out, s);
     if (p->variant == FFTC_VARIANT_TWO_PASS) return launch_two_pass(p, in, out, s);
     return launch_single(p, in, out, s);
 }
@@ -249,6 +284,7 @@ fftc_status fftc_destroy_plan(fftc_plan_t p) {
         hipError_t e = hipFree(p->scratch);
         if (e != hipSuccess) st = fail_hip(e, "hipFree(scratch)");
     }
+    if (p->mixed) destroy_mixed(p->mixed);
     delete p;
     return st;
 }
@@ -269,6 +305,14 @@ fftc_status fftc_plan_describe(fftc_plan_t p, fftc_plan_desc* d) {
     d->split_k = p->k;
     d->twiddle_bytes = p->tw_bytes;
     d->scratch_bytes = p->scratch_bytes;
+    if (p->mixed) {
+        d->mixed_transforms = p->mixed->count;
+        d->mixed_elements = p->mixed->total;
+        d->mixed_classes = (int)p->mixed->class_len.size();
+        d->mixed_items = p->mixed->nitems;
+        d->persistent_groups = p->mixed->groups;
+        d->twiddle_bytes = p->mixed->dev_bytes;
+    }
     return FFTC_OK;
 }
 
@@ -295,5 +339,50 @@ fftc_status fftc_factorize(int64_t n, int dtype, int* radices, int max_count, in
 }
 
 int64_t fftc_max_single_n(int dtype) { return max_single_n(dtype); }
+
+int fftc_compiled_count(int dtype) {
+    if (dtype != FFTC_C64 && dtype != FFTC_C128) return 0;
+    int total = 0;
+    for (int part = 0; part < kSpecParts; ++part) {
+        int cnt = 0;
+        spec_part(dtype, part, &cnt);
+        total += cnt;
+    }
+    return total;
+}
+
+fftc_status fftc_compiled_entry(int dtype, int i, int64_t* n, int* radices, int max_count, int* count) {
+    clear_error();
+    if (!n || !radices || !count) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
+    if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
+    int base = 0;
+    for (int part = 0; part < kSpecParts; ++part) {
+        int cnt = 0;
+        const SpecEntry* tab = spec_part(dtype, part, &cnt);
+        if (i >= base && i < base + cnt) {
+            const SpecEntry& e = tab[i - base];
+            if (e.nr > max_count) return fail(FFTC_ERR_INVALID_ARG, "max_count too small");
+            *n = e.n;
+            *count = e.nr;
+            for (int q = 0; q < e.nr; ++q) radices[q] = e.radices[q];
+            return FFTC_OK;
+        }
+        base += cnt;
+    }
+    return fail(FFTC_ERR_INVALID_ARG, "index out of range");
+}
+
+fftc_status fftc_candidates(int64_t n, int* radices, int* lens, int max_lists, int* nlists) {
+    clear_error();
+    if (!nlists || (max_lists > 0 && (!radices || !lens))) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
+    if (n < 2 || !is_7smooth(n) || n > (int64_t(1) << 20)) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "unsupported n");
+    auto c = radix_candidates(n, 12);
+    *nlists = (int)c.size();
+    for (int i = 0; i < (int)c.size() && i < max_lists; ++i) {
+        lens[i] = (int)c[i].size();
+        for (size_t q = 0; q < c[i].size(); ++q) radices[i * 16 + q] = c[i][q];
+    }
+    return FFTC_OK;
+}
 
 }  // extern "C"

@@ -10,8 +10,10 @@ extern "C" __shared__ __align__(16) unsigned char fftc_dyn_lds[];
 // ---------------------------------------------------------------------------
 // Runtime-length single kernel: one workgroup owns d.t transforms.
 // ---------------------------------------------------------------------------
-template <typename Real, bool INV>
-__global__ void __launch_bounds__(1024)
+// Up to 256 threads per workgroup: stage bodies inlined.  Larger groups
+// (lengths above 4096) call the bodies to stay within 128 registers.
+template <typename Real, bool INV, int MAXT>
+__global__ void __launch_bounds__(MAXT)
 stockham_generic(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __restrict__ tw,
                  int64_t batch, GenDesc d) {
     using C = cplx<Real>;
@@ -25,7 +27,7 @@ stockham_generic(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __rest
         if (valid && t == 0) out[off] = in[off];
         return;
     }
-    gen_transform<INV>(in + off, out + off, lds + tr * lds_len(d.n), tw, d, t, valid);
+    gen_transform<INV, (MAXT > 256)>(in + off, out + off, lds + tr * lds_len(d.n), tw, d, t, valid);
 }
 
 // ---------------------------------------------------------------------------
@@ -70,7 +72,7 @@ four_step_pass(const cplx<Real>* src, cplx<Real>* dst, const cplx<Real>* __restr
     __syncthreads();
     const int tr = (int)threadIdx.x / d.tpt;
     const int t = (int)threadIdx.x - tr * d.tpt;
-    gen_transform<false>((const C*)nullptr, (C*)nullptr, lds + tr * ldl, tw, d, t, true, false, false);
+    gen_transform<false, true>((const C*)nullptr, (C*)nullptr, lds + tr * ldl, tw, d, t, true, false, false);
     if (PASS == 1) {
         // row-major store z[(col0 + c) M + p] * w_N^{(col0 + c) p}; (col0+c) p < N
         for (int l = (int)threadIdx.x; l < tot; l += nthr) {
@@ -130,12 +132,19 @@ static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* o
         if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(stockham_spec)");
     } else {
         const int64_t groups = (batch + p->t - 1) / p->t;
-        if (inv)
-            hipLaunchKernelGGL((stockham_generic<Real, true>), dim3((unsigned)groups), dim3(p->tpt * p->t),
-                               p->lds_bytes, s, tin, tout, tw, batch, p->gdesc);
-        else
-            hipLaunchKernelGGL((stockham_generic<Real, false>), dim3((unsigned)groups), dim3(p->tpt * p->t),
-                               p->lds_bytes, s, tin, tout, tw, batch, p->gdesc);
+        const int threads = p->tpt * p->t;
+        dim3 g((unsigned)groups), b(threads);
+        if (threads <= 256) {
+            if (inv)
+                hipLaunchKernelGGL((stockham_generic<Real, true, 256>), g, b, p->lds_bytes, s, tin, tout, tw, batch, p->gdesc);
+            else
+                hipLaunchKernelGGL((stockham_generic<Real, false, 256>), g, b, p->lds_bytes, s, tin, tout, tw, batch, p->gdesc);
+        } else {
+            if (inv)
+                hipLaunchKernelGGL((stockham_generic<Real, true, 1024>), g, b, p->lds_bytes, s, tin, tout, tw, batch, p->gdesc);
+            else
+                hipLaunchKernelGGL((stockham_generic<Real, false, 1024>), g, b, p->lds_bytes, s, tin, tout, tw, batch, p->gdesc);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail_hip(e, "launch(stockham_generic)");
     }
@@ -215,8 +224,10 @@ fftc_status enable_large_lds() {
     static bool done = false;
     if (done) return FFTC_OK;
     const void* ks[] = {
-        (const void*)&stockham_generic<float, false>, (const void*)&stockham_generic<float, true>,
-        (const void*)&stockham_generic<double, false>, (const void*)&stockham_generic<double, true>,
+        (const void*)&stockham_generic<float, false, 256>, (const void*)&stockham_generic<float, true, 256>,
+        (const void*)&stockham_generic<double, false, 256>, (const void*)&stockham_generic<double, true, 256>,
+        (const void*)&stockham_generic<float, false, 1024>, (const void*)&stockham_generic<float, true, 1024>,
+        (const void*)&stockham_generic<double, false, 1024>, (const void*)&stockham_generic<double, true, 1024>,
         (const void*)&four_step_pass<float, false, 1>, (const void*)&four_step_pass<float, false, 2>,
         (const void*)&four_step_pass<float, true, 1>, (const void*)&four_step_pass<float, true, 2>,
         (const void*)&four_step_pass<double, false, 1>, (const void*)&four_step_pass<double, false, 2>,

@@ -77,6 +77,26 @@ __device__ __forceinline__ void gen_stage(const C* gin, C* gout, C* lds, const C
     if (!dst_global) __syncthreads();
 }
 
+// The same stage as a called (not inlined) function: a kernel whose stage
+// loop switches over seven inlined radix bodies lets their register ranges
+// pile up; calls keep each body's registers separate at a small call cost.
+template <int R, bool INV, typename C>
+__device__ __noinline__ void gen_stage_call(const C* gin, C* gout, C* lds, const C* __restrict__ tw,
+                                            StageRt s, int n, int tpt, int t, bool valid, bool src_global,
+                                            bool dst_global) {
+    gen_stage<R, INV>(gin, gout, lds, tw, s, n, tpt, t, valid, src_global, dst_global);
+}
+
+template <int R, bool INV, bool CALL, typename C>
+__device__ __forceinline__ void gen_stage_sel(const C* gin, C* gout, C* lds, const C* __restrict__ tw,
+                                              const StageRt& s, int n, int tpt, int t, bool valid,
+                                              bool src_global, bool dst_global) {
+    if constexpr (CALL)
+        gen_stage_call<R, INV>(gin, gout, lds, tw, s, n, tpt, t, valid, src_global, dst_global);
+    else
+        gen_stage<R, INV>(gin, gout, lds, tw, s, n, tpt, t, valid, src_global, dst_global);
+}
+
 // All stages of one transform.  Every thread of the workgroup must call this
 // (the stages synchronise the workgroup); `t` is the thread's index inside its
 // transform, `valid` whether it has a real transform to store (gin must point
@@ -84,7 +104,7 @@ __device__ __forceinline__ void gen_stage(const C* gin, C* gout, C* lds, const C
 // in_global the first stage reads gin (HBM), else the transform is already in
 // lds; with out_global the last stage writes gout, else it leaves the result
 // in lds in natural order.
-template <bool INV, typename C>
+template <bool INV, bool CALL = false, typename C>
 __device__ __forceinline__ void gen_transform(const C* gin, C* gout, C* lds, const C* __restrict__ tw,
                                               const GenDesc& d, int t, bool valid, bool in_global = true,
                                               bool out_global = true) {
@@ -92,13 +112,13 @@ __device__ __forceinline__ void gen_transform(const C* gin, C* gout, C* lds, con
         const StageRt s = d.st[q];
         const bool first = (q == 0) && in_global, last = (q == d.nst - 1) && out_global;
         switch (s.r) {
-            case 2: gen_stage<2, INV>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
-            case 3: gen_stage<3, INV>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
-            case 4: gen_stage<4, INV>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
-            case 5: gen_stage<5, INV>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
-            case 7: gen_stage<7, INV>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
-            case 8: gen_stage<8, INV>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
-            default: gen_stage<16, INV>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
+            case 2: gen_stage_sel<2, INV, CALL>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
+            case 3: gen_stage_sel<3, INV, CALL>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
+            case 4: gen_stage_sel<4, INV, CALL>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
+            case 5: gen_stage_sel<5, INV, CALL>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
+            case 7: gen_stage_sel<7, INV, CALL>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
+            case 8: gen_stage_sel<8, INV, CALL>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
+            default: gen_stage_sel<16, INV, CALL>(gin, gout, lds, tw, s, d.n, d.tpt, t, valid, first, last); break;
         }
     }
 }

@@ -32,9 +32,14 @@ std::vector<std::vector<int>> radix_candidates(int64_t n, int max_lists = 12);
 void launch_shape(int64_t n, const std::vector<int>& rs, int csize, int* tpt, int* t);
 // Two-pass split n = m k (pass 1: k columns of length m; pass 2: m of length k).
 bool two_pass_split(int64_t n, int dtype, int64_t* m, int64_t* k);
+// Radix list a plan uses: the tuning database's entry, else candidates[0].
+std::vector<int> choose_radices(int64_t n, int dtype);
 // Tuning database: best radix list for (n, dtype), if recorded.
 bool tune_lookup(int64_t n, int dtype, std::vector<int>* rs);
 void tune_record(int64_t n, int dtype, const std::vector<int>& rs, double ms);
+int tune_load_file(const char* path);
+int tune_save_file(const char* path);
+void tune_clear_all();
 
 // ---- kernels ----------------------------------------------------------------
 struct SpecEntry {
@@ -43,10 +48,11 @@ struct SpecEntry {
     int tpt, t;
     const void* fwd;
     const void* inv;
+    int id;  // index in the dtype's compiled list (body id in mixed kernels)
 };
-// Compiled specialisations (kernels_c64.hip / kernels_c128.hip).
-const SpecEntry* spec_table_c64(int* count);
-const SpecEntry* spec_table_c128(int* count);
+// Compiled specialisations, in kSpecParts translation units per dtype.
+constexpr int kSpecParts = 4;
+const SpecEntry* spec_part(int dtype, int part, int* count);
 const SpecEntry* find_spec(int dtype, int64_t n, const std::vector<int>& rs);
 
 struct TwSegment {

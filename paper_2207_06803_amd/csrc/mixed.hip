@@ -1,0 +1,220 @@
+// Mixed-length batches in one persistent launch: plan construction.
+//
+// Transforms of different lengths N_i are packed back to back (offset =
+// prefix sum of the lengths).  Transforms of equal length form a class with
+// its own Stockham radix list (from the tuning database or the planner) and
+// twiddle segment in one shared table.  Work items hold up to T_c transforms
+// of one class -- as many as one 256-thread workgroup can hold in registers
+// and LDS -- and are ordered by decreasing cost (longest processing time
+// first).  A grid sized to fill the GPU once pulls items from an atomic
+// counter until the list is exhausted; every workgroup leaves the loop after
+// reading an index past the end.  The counter is cleared by a small kernel in
+// front of the persistent kernel; both are recorded in a hipGraph at plan
+// time and relaunched per execution.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+
+#include "plan.h"
+
+namespace fftc {
+
+__global__ void mixed_reset(unsigned int* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+static const void* mixed_fn(int dtype, int direction) {
+    const bool inv = direction == FFTC_INVERSE;
+    return dtype == FFTC_C128 ? mixed_kernel_c128(inv) : mixed_kernel_c64(inv);
+}
+
+static void free_mixed(MixedState* m) {
+    if (!m) return;
+    if (m->exec) hipGraphExecDestroy(m->exec);
+    if (m->graph) hipGraphDestroy(m->graph);
+    if (m->dev) hipFree(m->dev);
+    delete m;
+}
+
+void destroy_mixed(MixedState* m) { free_mixed(m); }
+
+fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count) {
+    const int dtype = p->dtype;
+    const size_t cs = dtype == FFTC_C128 ? 16 : 8;
+    MixedState* m = new (std::nothrow) MixedState();
+    if (!m) return fail(FFTC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->mixed = m;
+
+    // classes, offsets
+    std::map<int64_t, int> cls_of;
+    std::vector<int64_t> offsets(count);
+    int64_t total = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        offsets[i] = total;
+        total += n[i];
+        if (!cls_of.count(n[i])) cls_of[n[i]] = 0;
+    }
+    std::vector<int64_t> lens;
+    for (auto& kv : cls_of) {
+        kv.second = (int)lens.size();
+        lens.push_back(kv.first);
+    }
+    const int ncls = (int)lens.size();
+    std::vector<MixedClass> classes(ncls);
+    std::vector<TwSegment> segs;
+    int64_t twoff = 0;
+    size_t lds_need = 0;
+    for (int c = 0; c < ncls; ++c) {
+        const int64_t len = lens[c];
+        std::vector<int> rs;
+        if (len > 1) rs = choose_radices(len, dtype);
+        if (len > 1 && rs.empty()) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no factorisation");
+        int tpt, t;
+        const int64_t per = rs.size() > 1 ? lds_len((int)len) : 0;
+        const SpecEntry* spec = len > 1 ? find_spec(dtype, len, rs) : nullptr;
+        int64_t ldsn = per;
+        if (spec && spec->tpt * spec->t <= kMixedThreads) {
+            // compiled body: its own launch shape; short lists stage through LDS
+            tpt = spec->tpt;
+            t = spec->t;
+            classes[c].body = spec->id;
+            ldsn = lds_len((int)len);
+        } else {
+            launch_shape(len, rs, (int)cs, &tpt, &t);
+            if (tpt > kMixedThreads) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "radix list needs too many threads");
+            // transforms per item: fill the workgroup and the per-item LDS budget
+            t = std::max(1, kMixedThreads / tpt);
+            if (per > 0) t = (int)std::min<int64_t>(t, std::max<int64_t>(1, kMixedLdsElems / per));
+            classes[c].body = -1;
+        }
+        classes[c].twbase = (int)twoff;
+        classes[c].ldsn = (int)ldsn;
+        const int64_t used = stage_segments(rs, twoff, &segs);
+        fill_gen_desc(len, rs, tpt, t, twoff, &classes[c].desc);
+        twoff += used;
+        lds_need = std::max(lds_need, (size_t)(ldsn * t) * cs);
+        m->class_len.push_back(len);
+        m->class_radices.push_back(rs);
+    }
+    // items: per class, chunks of up to t transforms, in input order
+    std::vector<std::vector<int64_t>> members(ncls);
+    for (int64_t i = 0; i < count; ++i) members[cls_of[n[i]]].push_back(i);
+    std::vector<int64_t> order;  // transform ids grouped by class
+    std::vector<MixedItem> items;
+    std::vector<double> cost;
+    for (int c = 0; c < ncls; ++c) {
+        const int t = classes[c].desc.t;
+        const double per = (double)lens[c] * std::log2((double)lens[c]);
+        for (size_t s = 0; s < members[c].size(); s += t) {
+            MixedItem it{};
+            it.cls = c;
+            it.first = (int)order.size();
+            it.count = (int)std::min<size_t>(t, members[c].size() - s);
+            for (int q = 0; q < it.count; ++q) order.push_back(members[c][s + q]);
+            items.push_back(it);
+            cost.push_back(per * it.count);
+        }
+    }
+    // longest processing time first
+    std::vector<size_t> idx(items.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<MixedItem> sorted(items.size());
+    for (size_t i = 0; i < idx.size(); ++i) sorted[i] = items[idx[i]];
+    std::vector<int64_t> toffs(order.size());
+    for (size_t i = 0; i < order.size(); ++i) toffs[i] = offsets[order[i]];
+
+    m->count = count;
+    m->total = total;
+    m->nitems = (int)sorted.size();
+    m->lds_bytes = std::max<size_t>(lds_need, 16);
+
+    // device block: counter | classes | items | offsets | twiddles
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_cnt = 0;
+    const size_t o_cls = align(o_cnt + sizeof(unsigned int));
+    const size_t o_items = align(o_cls + sizeof(MixedClass) * ncls);
+    const size_t o_offs = align(o_items + sizeof(MixedItem) * sorted.size());
+    const size_t o_tw = align(o_offs + sizeof(int64_t) * toffs.size());
+    const size_t bytes = o_tw + (size_t)std::max<int64_t>(twoff, 1) * cs;
+    FFTC_HIP_TRY(hipMalloc(&m->dev, bytes));
+    m->dev_bytes = bytes;
+    char* base = static_cast<char*>(m->dev);
+    m->counter = reinterpret_cast<unsigned int*>(base + o_cnt);
+    m->d_classes = reinterpret_cast<MixedClass*>(base + o_cls);
+    m->d_items = reinterpret_cast<MixedItem*>(base + o_items);
+    m->d_offsets = reinterpret_cast<int64_t*>(base + o_offs);
+    m->d_tw = base + o_tw;
+    FFTC_HIP_TRY(hipMemcpy(m->d_classes, classes.data(), sizeof(MixedClass) * ncls, hipMemcpyHostToDevice));
+    FFTC_HIP_TRY(hipMemcpy(m->d_items, sorted.data(), sizeof(MixedItem) * sorted.size(), hipMemcpyHostToDevice));
+    FFTC_HIP_TRY(hipMemcpy(m->d_offsets, toffs.data(), sizeof(int64_t) * toffs.size(), hipMemcpyHostToDevice));
+    FFTC_HIP_TRY(hipMemset(m->counter, 0, sizeof(unsigned int)));
+    fftc_status st = make_twiddles(m->d_tw, dtype, segs, nullptr);
+    if (st != FFTC_OK) return st;
+
+    // persistent grid: every resident workgroup slot once
+    const void* fn = mixed_fn(dtype, p->direction);
+    FFTC_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->lds_bytes));
+    int per_cu = 0, dev = 0, cus = 0;
+    FFTC_HIP_TRY(hipGetDevice(&dev));
+    FFTC_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    FFTC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kMixedThreads, m->lds_bytes));
+    m->groups = std::max(1, std::min(per_cu * cus, m->nitems));
+
+    // graph: reset counter -> persistent kernel
+    FFTC_HIP_TRY(hipGraphCreate(&m->graph, 0));
+    {
+        hipKernelNodeParams kp{};
+        void* args[] = {&m->counter};
+        kp.func = reinterpret_cast<void*>(&mixed_reset);
+        kp.gridDim = dim3(1);
+        kp.blockDim = dim3(64);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        FFTC_HIP_TRY(hipGraphAddKernelNode(&m->reset_node, m->graph, nullptr, 0, &kp));
+    }
+    {
+        m->args.in = nullptr;
+        m->args.out = nullptr;
+        hipKernelNodeParams kp = m->kernel_params(fn);
+        FFTC_HIP_TRY(hipGraphAddKernelNode(&m->kernel_node, m->graph, &m->reset_node, 1, &kp));
+    }
+    FFTC_HIP_TRY(hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
+    m->fn = fn;
+    return FFTC_OK;
+}
+
+hipKernelNodeParams MixedState::kernel_params(const void* fn_) {
+    kargs[0] = &args.in;
+    kargs[1] = &args.out;
+    kargs[2] = &d_tw;
+    kargs[3] = &d_classes;
+    kargs[4] = &d_items;
+    kargs[5] = &d_offsets;
+    kargs[6] = &nitems;
+    kargs[7] = &counter;
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(fn_);
+    kp.gridDim = dim3((unsigned)groups);
+    kp.blockDim = dim3(kMixedThreads);
+    kp.sharedMemBytes = (unsigned)lds_bytes;
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    return kp;
+}
+
+fftc_status launch_mixed(fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
+    MixedState* m = p->mixed;
+    if (in != m->args.in || out != m->args.out) {
+        m->args.in = in;
+        m->args.out = out;
+        hipKernelNodeParams kp = m->kernel_params(m->fn);
+        FFTC_HIP_TRY(hipGraphExecKernelNodeSetParams(m->exec, m->kernel_node, &kp));
+    }
+    FFTC_HIP_TRY(hipGraphLaunch(m->exec, s));
+    return FFTC_OK;
+}
+
+}  // namespace fftc

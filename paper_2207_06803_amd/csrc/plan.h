@@ -4,6 +4,7 @@
 
 #include "generic.h"
 #include "internal.h"
+#include "mixed.h"
 
 struct fftc_plan_s {
     int64_t n = 0, batch = 0;
@@ -25,12 +26,17 @@ struct fftc_plan_s {
     int64_t tw1_off = 0, tw2_off = 0, twn_off = 0;  // table offsets (elements)
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // mixed-length persistent plan
+    fftc::MixedState* mixed = nullptr;
 };
 
 namespace fftc {
 
 fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, hipStream_t s);
 fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, hipStream_t s);
+fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count);
+fftc_status launch_mixed(fftc_plan_s* p, const void* in, void* out, hipStream_t s);
+void destroy_mixed(MixedState* m);
 // Fill a runtime descriptor for a radix list (twoff relative to twbase).
 void fill_gen_desc(int64_t n, const std::vector<int>& rs, int tpt, int t, int64_t twbase, GenDesc* d);
 

@@ -125,40 +125,62 @@ bool two_pass_split(int64_t n, int dtype, int64_t* m_out, int64_t* k_out) {
     return true;
 }
 
+std::vector<int> choose_radices(int64_t n, int dtype) {
+    std::vector<int> rs;
+    if (tune_lookup(n, dtype, &rs)) return rs;
+    auto c = radix_candidates(n, 1);
+    return c.empty() ? rs : c[0];
+}
+
 // ---- tuning database ----------------------------------------------------------
-// Text file, one line per entry:  <arch> <dtype> <n> <r1,r2,...> <ms>
+// Text file, one line per entry:  <arch> <c64|c128> <n> <r1,r2,...> <ms>
+// Entries for another architecture are ignored; a list that does not multiply
+// to n is ignored.
 namespace {
 std::mutex g_tune_mu;
 std::map<std::pair<int64_t, int>, std::pair<std::vector<int>, double>> g_tune;
-bool g_tune_loaded = false;
-std::string g_tune_arch = "gfx950";
+bool g_tune_env_done = false;
+const char* kTuneArch = "gfx950";
 
-void load_env_db_locked() {
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char* p = getenv("FFTC_TUNE_DB");
-    if (!p || !*p) return;
-    FILE* f = fopen(p, "r");
-    if (!f) return;
+int load_locked(const char* path) {
+    FILE* f = fopen(path, "r");
+    if (!f) return -1;
     char arch[64], dt[16], rl[256];
     long long n;
     double ms;
+    int added = 0;
     while (fscanf(f, "%63s %15s %lld %255s %lf", arch, dt, &n, rl, &ms) == 5) {
-        if (g_tune_arch != arch) continue;
+        if (strcmp(arch, kTuneArch) != 0) continue;
         const int dtype = strcmp(dt, "c128") == 0 ? FFTC_C128 : FFTC_C64;
         std::vector<int> rs;
-        for (char* tok = strtok(rl, ","); tok; tok = strtok(nullptr, ",")) rs.push_back(atoi(tok));
         int64_t prod = 1;
-        for (int r : rs) prod *= r;
-        if (prod == n) g_tune[{n, dtype}] = {rs, ms};
+        bool ok = true;
+        for (char* tok = strtok(rl, ","); tok; tok = strtok(nullptr, ",")) {
+            const int r = atoi(tok);
+            ok = ok && (r == 2 || r == 3 || r == 4 || r == 5 || r == 7 || r == 8 || r == 16);
+            rs.push_back(r);
+            prod *= r;
+        }
+        if (ok && prod == n && (int)rs.size() <= kMaxStages) {
+            g_tune[{(int64_t)n, dtype}] = {rs, ms};
+            ++added;
+        }
     }
     fclose(f);
+    return added;
+}
+
+void env_locked() {
+    if (g_tune_env_done) return;
+    g_tune_env_done = true;
+    const char* p = getenv("FFTC_TUNE_DB");
+    if (p && *p) load_locked(p);
 }
 }  // namespace
 
 bool tune_lookup(int64_t n, int dtype, std::vector<int>* rs) {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    load_env_db_locked();
+    env_locked();
     auto it = g_tune.find({n, dtype});
     if (it == g_tune.end()) return false;
     *rs = it->second.first;
@@ -167,30 +189,35 @@ bool tune_lookup(int64_t n, int dtype, std::vector<int>* rs) {
 
 void tune_record(int64_t n, int dtype, const std::vector<int>& rs, double ms) {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    load_env_db_locked();
+    env_locked();
     g_tune[{n, dtype}] = {rs, ms};
 }
 
-int tune_save(const char* path) {
+int tune_load_file(const char* path) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    env_locked();
+    return load_locked(path);
+}
+
+int tune_save_file(const char* path) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     FILE* f = fopen(path, "w");
     if (!f) return -1;
     for (auto& kv : g_tune) {
-        fprintf(f, "%s %s %lld ", g_tune_arch.c_str(), kv.first.second == FFTC_C128 ? "c128" : "c64",
+        fprintf(f, "%s %s %lld ", kTuneArch, kv.first.second == FFTC_C128 ? "c128" : "c64",
                 (long long)kv.first.first);
         const auto& rs = kv.second.first;
         for (size_t i = 0; i < rs.size(); ++i) fprintf(f, i ? ",%d" : "%d", rs[i]);
         fprintf(f, " %.6f\n", kv.second.second);
     }
     fclose(f);
-    return 0;
+    return (int)g_tune.size();
 }
 
-int tune_clear() {
+void tune_clear_all() {
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune.clear();
-    g_tune_loaded = true;
-    return 0;
+    g_tune_env_done = true;
 }
 
 int64_t stage_segments(const std::vector<int>& rs, int64_t base, std::vector<TwSegment>* segs) {

@@ -1,0 +1,16 @@
+// Compiled c64 Stockham specialisations, part 0 of the list in spec_list.inc.
+#include "spec_list.inc"
+#include "spec_table.h"
+
+namespace fftc {
+
+#define E(ID, N, ...) SpecInst<float, N, __VA_ARGS__>::entry(FFTC_C64, ID),
+static const SpecEntry k_table[] = {FFTC_SPEC_LIST_C64_PART0(E)};
+#undef E
+
+const SpecEntry* spec_part_c64_0(int* count) {
+    *count = (int)(sizeof(k_table) / sizeof(k_table[0]));
+    return k_table;
+}
+
+}  // namespace fftc

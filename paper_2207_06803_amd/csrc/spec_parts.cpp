@@ -1,0 +1,20 @@
+// Registry of the compiled Stockham specialisations (all parts, both dtypes).
+#include "internal.h"
+
+namespace fftc {
+
+#define DECL(dt, p) const SpecEntry* spec_part_##dt##_##p(int* count);
+DECL(c64, 0) DECL(c64, 1) DECL(c64, 2) DECL(c64, 3)
+DECL(c128, 0) DECL(c128, 1) DECL(c128, 2) DECL(c128, 3)
+#undef DECL
+
+const SpecEntry* spec_part(int dtype, int part, int* count) {
+    using Fn = const SpecEntry* (*)(int*);
+    static const Fn c64[kSpecParts] = {spec_part_c64_0, spec_part_c64_1, spec_part_c64_2, spec_part_c64_3};
+    static const Fn c128[kSpecParts] = {spec_part_c128_0, spec_part_c128_1, spec_part_c128_2, spec_part_c128_3};
+    *count = 0;
+    if (part < 0 || part >= kSpecParts) return nullptr;
+    return dtype == FFTC_C128 ? c128[part](count) : c64[part](count);
+}
+
+}  // namespace fftc

@@ -1,5 +1,7 @@
 // Registry entries for compile-time specialised Stockham kernels.
 #pragma once
+#include <type_traits>
+
 #include "internal.h"
 #include "stockham.h"
 
@@ -12,16 +14,31 @@ struct SpecInst {
     static constexpr int TPT = round_tpt(required_tpt(N, rs, NR));
     static constexpr int T = pick_t(TPT, N, (int)sizeof(cplx<Real>), NR > 1);
     static_assert(TPT * T <= 1024, "workgroup too large");
-    static_assert((NR > 1 ? T * lds_len(N) * (int)sizeof(cplx<Real>) : 0) <= kLdsMaxPerGroup,
-                  "LDS too large");
+    static_assert(T * lds_len(N) * (int)sizeof(cplx<Real>) <= kLdsMaxPerGroup, "LDS too large");
     using KF = SpecCfg<Real, N, TPT, T, false>;
     using KI = SpecCfg<Real, N, TPT, T, true>;
-    static SpecEntry entry(int dtype) {
+    template <bool INV> using K = typename std::conditional<INV, KI, KF>::type;
+    static SpecEntry entry(int dtype, int id) {
         SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
                     reinterpret_cast<const void*>(&stockham_spec<KF, Rs...>),
-                    reinterpret_cast<const void*>(&stockham_spec<KI, Rs...>)};
+                    reinterpret_cast<const void*>(&stockham_spec<KI, Rs...>), id};
         return e;
     }
 };
+
+// One work item of a compiled list inside the persistent mixed-length kernel:
+// `count` transforms at offsets offs[0..count) (not inlined, so each body
+// keeps its own registers).
+struct ListOff {
+    const int64_t* offs;
+    __device__ __forceinline__ int64_t operator()(int q) const { return offs[q]; }
+};
+
+template <class K, int NTH, int... Rs>
+__device__ __noinline__ void spec_body(const typename K::C* in, typename K::C* out, const int64_t* offs,
+                                       int count, typename K::C* lds, const typename K::C* __restrict__ tw,
+                                       int tid) {
+    spec_group<K, NTH, ListOff, Rs...>(in, out, ListOff{offs}, count, lds, tw, tid);
+}
 
 }  // namespace fftc

@@ -42,18 +42,26 @@ template <bool INV, typename C> __device__ __forceinline__ void st_out(C* p, C v
 // Compile-time specialised kernel: N, radix sequence, threads per transform
 // (TPT) and transforms per workgroup (T) are template parameters, so every
 // index division folds to shifts / multiplies.
+//
+// With TPT >= 16 the first stage reads HBM and the last writes it directly
+// (each wave access covers >= 128 contiguous bytes per transform).  Below
+// that (short transforms, many per group) the group's transforms are staged:
+// loaded cooperatively with consecutive lanes on consecutive elements into
+// LDS, transformed LDS to LDS, and stored back the same way.
 // ---------------------------------------------------------------------------
 template <typename Real, int N_, int TPT_, int T_, bool INV_>
 struct SpecCfg {
     using C = cplx<Real>;
     static constexpr int N = N_, TPT = TPT_, T = T_;
     static constexpr bool INV = INV_;
+    static constexpr bool STAGED = TPT_ < 16;
 };
 
-template <class K, int R, int NS, int TWOFF, bool FIRST, bool LAST>
+template <class K, int R, int NS, int TWOFF, bool SRC_G, bool DST_G>
 __device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K::C* gout,
                                            typename K::C* lds,
-                                           const typename K::C* __restrict__ tw, int t, bool valid) {
+                                           const typename K::C* __restrict__ tw, int t, bool valid,
+                                           bool active) {
     using C = typename K::C;
     constexpr int N = K::N, TPT = K::TPT;
     constexpr int NR = N / R;
@@ -63,12 +71,12 @@ __device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K:
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int j = t + i * TPT;
-        if (EVEN || j < NR) {
+        if (active && (EVEN || j < NR)) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if constexpr (FIRST) {
-                    // unconditional: the caller clamps gin to a real transform
-                    // for out-of-range groups, whose results are never stored
+                if constexpr (SRC_G) {
+                    // unconditional: the caller points gin at a real transform
+                    // for out-of-range slots, whose results are never stored
                     v[i][r] = ld_in<K::INV>(gin + j + r * NR);
                 } else {
                     v[i][r] = lds[lds_pad(j + r * NR)];
@@ -82,16 +90,16 @@ __device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K:
             Codelet<R, C>::run(v[i]);
         }
     }
-    if constexpr (!FIRST) __syncthreads();
+    if constexpr (!SRC_G) __syncthreads();
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int j = t + i * TPT;
-        if (EVEN || j < NR) {
+        if (active && (EVEN || j < NR)) {
             const int k = j % NS;
             const int base = (j / NS) * NS * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if constexpr (LAST) {
+                if constexpr (DST_G) {
                     if (valid) st_out<K::INV>(gout + base + r * NS, v[i][r]);
                 } else {
                     lds[lds_pad(base + r * NS)] = v[i][r];
@@ -99,34 +107,82 @@ __device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K:
             }
         }
     }
-    if constexpr (!LAST) __syncthreads();
+    if constexpr (!DST_G) __syncthreads();
 }
 
-template <class K, int NS, int TWOFF, bool FIRST, int R, int... Rest>
+template <class K, int NS, int TWOFF, bool FIRST, bool SG, bool DG, int R, int... Rest>
 __device__ __forceinline__ void spec_stages(const typename K::C* gin, typename K::C* gout,
                                             typename K::C* lds,
-                                            const typename K::C* __restrict__ tw, int t, bool valid) {
+                                            const typename K::C* __restrict__ tw, int t, bool valid,
+                                            bool active) {
     constexpr bool LAST = sizeof...(Rest) == 0;
-    spec_stage<K, R, NS, TWOFF, FIRST, LAST>(gin, gout, lds, tw, t, valid);
+    spec_stage<K, R, NS, TWOFF, FIRST && SG, LAST && DG>(gin, gout, lds, tw, t, valid, active);
     if constexpr (!LAST)
-        spec_stages<K, NS * R, TWOFF + (R - 1) * NS, false, Rest...>(gin, gout, lds, tw, t, valid);
+        spec_stages<K, NS * R, TWOFF + (R - 1) * NS, false, SG, DG, Rest...>(gin, gout, lds, tw, t, valid,
+                                                                          active);
 }
+
+template <class K, int NR> struct SpecLds {
+    static constexpr int LDSN = (NR > 1 || K::STAGED) ? lds_len(K::N) : 1;
+};
+
+// The transforms of one group: transform q < count starts at element toff(q)
+// of in and out.  All NTH threads of the workgroup call this (NTH >= TPT T).
+template <class K, int NTH, class OffF, int... Rs>
+__device__ __forceinline__ void spec_group(const typename K::C* in, typename K::C* out, OffF toff, int count,
+                                           typename K::C* lds, const typename K::C* __restrict__ tw, int tid) {
+    using C = typename K::C;
+    constexpr int N = K::N, TPT = K::TPT, T = K::T;
+    constexpr int LDSN = SpecLds<K, sizeof...(Rs)>::LDSN;
+    const int tr = (T == 1) ? (tid < TPT ? 0 : 1) : tid / TPT;
+    const int t = (T == 1) ? tid : tid - tr * TPT;
+    const bool member = tr < T;
+    const bool valid = member && tr < count;
+    C* mylds = lds + (member ? tr : 0) * LDSN;
+    if constexpr (K::STAGED) {
+        constexpr int TOT = T * N;
+        constexpr int ITER = (TOT + NTH - 1) / NTH;
+        C buf[ITER];
+#pragma unroll
+        for (int i = 0; i < ITER; ++i) {
+            const int l = tid + i * NTH;
+            const int q = min(l / N, count - 1);  // clamp: always a real transform
+            buf[i] = ld_in<K::INV>(in + toff(q) + (l % N));
+        }
+#pragma unroll
+        for (int i = 0; i < ITER; ++i) {
+            const int l = tid + i * NTH;
+            if (l < TOT) lds[(l / N) * LDSN + lds_pad(l % N)] = buf[i];
+        }
+        __syncthreads();
+        spec_stages<K, 1, 0, true, false, false, Rs...>(nullptr, nullptr, mylds, tw, t, valid, member);
+#pragma unroll
+        for (int i = 0; i < ITER; ++i) {
+            const int l = tid + i * NTH;
+            const int q = l / N;
+            if (l < TOT && q < count) st_out<K::INV>(out + toff(q) + (l % N), lds[q * LDSN + lds_pad(l % N)]);
+        }
+    } else {
+        const int64_t off = toff(valid ? tr : 0);
+        spec_stages<K, 1, 0, true, true, true, Rs...>(in + off, out + off, mylds, tw, t, valid, member);
+    }
+}
+
+struct ContigOff {
+    int64_t base, n;
+    __device__ __forceinline__ int64_t operator()(int q) const { return base + (int64_t)q * n; }
+};
 
 template <class K, int... Rs>
 __global__ void __launch_bounds__(K::TPT * K::T)
 stockham_spec(const typename K::C* in, typename K::C* out,
               const typename K::C* __restrict__ tw, int64_t batch) {
     using C = typename K::C;
-    constexpr int N = K::N, TPT = K::TPT, T = K::T;
-    constexpr bool MULTI = sizeof...(Rs) > 1;
-    constexpr int LDSN = MULTI ? lds_len(N) : 1;
-    __shared__ C lds[T * LDSN];
-    const int tr = (T == 1) ? 0 : (int)(threadIdx.x / TPT);
-    const int t = (T == 1) ? (int)threadIdx.x : (int)(threadIdx.x % TPT);
-    const int64_t b = (int64_t)blockIdx.x * T + tr;
-    const bool valid = b < batch;
-    const int64_t off = (valid ? b : 0) * (int64_t)N;
-    spec_stages<K, 1, 0, true, Rs...>(in + off, out + off, lds + tr * LDSN, tw, t, valid);
+    constexpr int N = K::N, T = K::T, NTH = K::TPT * K::T;
+    __shared__ C lds[T * SpecLds<K, sizeof...(Rs)>::LDSN];
+    const int64_t b0 = (int64_t)blockIdx.x * T;
+    const int count = (int)min((int64_t)T, batch - b0);
+    spec_group<K, NTH, ContigOff, Rs...>(in, out, ContigOff{b0 * N, N}, count, lds, tw, (int)threadIdx.x);
 }
 
 }  // namespace fftc

@@ -20,7 +20,7 @@ C64 = 0
 C128 = 1
 DTYPES = {"c64": C64, "complex64": C64, C64: C64, "c128": C128, "complex128": C128, C128: C128}
 
-VARIANT_NAMES = {0: "single_specialised", 1: "single_generic", 2: "two_pass"}
+VARIANT_NAMES = {0: "single_specialised", 1: "single_generic", 2: "two_pass", 3: "mixed_persistent"}
 
 STATUS = {0: "FFTC_OK", 1: "FFTC_ERR_INVALID_ARG", 2: "FFTC_ERR_UNSUPPORTED_SIZE",
           3: "FFTC_ERR_OUT_OF_MEMORY", 4: "FFTC_ERR_TOO_LARGE", 5: "FFTC_ERR_HIP",
@@ -39,7 +39,9 @@ class PlanDesc(ctypes.Structure):
                 ("radices", ctypes.c_int * 16), ("threads_per_transform", ctypes.c_int),
                 ("transforms_per_group", ctypes.c_int), ("split_m", ctypes.c_int64),
                 ("split_k", ctypes.c_int64), ("twiddle_bytes", ctypes.c_size_t),
-                ("scratch_bytes", ctypes.c_size_t)]
+                ("scratch_bytes", ctypes.c_size_t), ("mixed_transforms", ctypes.c_int64),
+                ("mixed_elements", ctypes.c_int64), ("mixed_classes", ctypes.c_int),
+                ("mixed_items", ctypes.c_int), ("persistent_groups", ctypes.c_int)]
 
 
 _i64, _int, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
@@ -52,6 +54,16 @@ _SIGNATURES = {
     "fftc_factorize": (_int, [_i64, _int, ctypes.POINTER(_int), _int, ctypes.POINTER(_int),
                               ctypes.POINTER(_i64)]),
     "fftc_max_single_n": (_i64, [_int]),
+    "fftc_compiled_count": (_int, [_int]),
+    "fftc_compiled_entry": (_int, [_int, _int, ctypes.POINTER(_i64), ctypes.POINTER(_int), _int,
+                                   ctypes.POINTER(_int)]),
+    "fftc_candidates": (_int, [_i64, ctypes.POINTER(_int), ctypes.POINTER(_int), _int, ctypes.POINTER(_int)]),
+    "fftc_plan_mixed": (_int, [ctypes.POINTER(_i64), _i64, _int, _int, ctypes.POINTER(_vp)]),
+    "fftc_autotune": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(_int), _int, ctypes.POINTER(_int),
+                             ctypes.POINTER(ctypes.c_double)]),
+    "fftc_tune_load": (_int, [ctypes.c_char_p, ctypes.POINTER(_int)]),
+    "fftc_tune_save": (_int, [ctypes.c_char_p, ctypes.POINTER(_int)]),
+    "fftc_tune_clear": (_int, []),
     "fftc_status_string": (ctypes.c_char_p, [_int]),
     "fftc_last_error": (ctypes.c_char_p, []),
 }
@@ -127,9 +139,14 @@ def dtype_code(dtype) -> int:
 class Plan:
     """Owns an fftc_plan_t; destroyed by close() or garbage collection."""
 
-    def __init__(self, n: int, batch: int, direction: int = FORWARD, dtype="c64", radices=None):
-        h = _vp()
+    def __init__(self, n: int, batch: int, direction: int = FORWARD, dtype="c64", radices=None,
+                 _handle=None):
         code = dtype_code(dtype)
+        if _handle is not None:
+            self._h = _handle
+            self.n, self.batch, self.direction, self.dtype = n, batch, direction, code
+            return
+        h = _vp()
         if radices is None:
             check(lib.fftc_plan(n, batch, direction, code, ctypes.byref(h)), "fftc_plan")
         else:
@@ -156,7 +173,10 @@ class Plan:
                 "threads_per_transform": d.threads_per_transform,
                 "transforms_per_group": d.transforms_per_group,
                 "split_m": d.split_m, "split_k": d.split_k,
-                "twiddle_bytes": d.twiddle_bytes, "scratch_bytes": d.scratch_bytes}
+                "twiddle_bytes": d.twiddle_bytes, "scratch_bytes": d.scratch_bytes,
+                "mixed_transforms": d.mixed_transforms, "mixed_elements": d.mixed_elements,
+                "mixed_classes": d.mixed_classes, "mixed_items": d.mixed_items,
+                "persistent_groups": d.persistent_groups}
 
     def close(self) -> None:
         if self._h is not None and self._h.value:
@@ -177,6 +197,46 @@ class Plan:
         self.close()
 
 
+def plan_mixed(lengths, direction: int = FORWARD, dtype="c64") -> Plan:
+    """One persistent-launch plan for transforms of the given lengths, packed
+    back to back in that order."""
+    lens = [int(v) for v in lengths]
+    arr = (_i64 * len(lens))(*lens)
+    h = _vp()
+    check(lib.fftc_plan_mixed(arr, len(lens), direction, dtype_code(dtype), ctypes.byref(h)),
+          "fftc_plan_mixed")
+    p = Plan(0, len(lens), direction, dtype, _handle=h)
+    p.lengths = lens
+    return p
+
+
+def autotune(n: int, batch: int, dtype="c64", reps: int = 10):
+    """Time every candidate radix list for n on the device; record and return
+    the fastest (list, microseconds per launch)."""
+    arr = (_int * 32)()
+    cnt = _int()
+    us = ctypes.c_double()
+    check(lib.fftc_autotune(n, batch, dtype_code(dtype), reps, arr, 32, ctypes.byref(cnt),
+                            ctypes.byref(us)), "fftc_autotune")
+    return list(arr[:cnt.value]), us.value
+
+
+def tune_load(path: str) -> int:
+    k = _int()
+    check(lib.fftc_tune_load(path.encode(), ctypes.byref(k)), "fftc_tune_load")
+    return k.value
+
+
+def tune_save(path: str) -> int:
+    k = _int()
+    check(lib.fftc_tune_save(path.encode(), ctypes.byref(k)), "fftc_tune_save")
+    return k.value
+
+
+def tune_clear() -> None:
+    check(lib.fftc_tune_clear(), "fftc_tune_clear")
+
+
 def factorize(n: int, dtype="c64"):
     """Radix list the planner picks for n (host only), and the two-pass split m (0 if none)."""
     arr = (_int * 32)()
@@ -185,6 +245,29 @@ def factorize(n: int, dtype="c64"):
     check(lib.fftc_factorize(n, dtype_code(dtype), arr, 32, ctypes.byref(cnt), ctypes.byref(m)),
           "fftc_factorize")
     return list(arr[:cnt.value]), m.value
+
+
+def candidates(n: int):
+    """Candidate radix lists for single-kernel length n, preference order."""
+    flat = (_int * (16 * 12))()
+    lens = (_int * 12)()
+    cnt = _int()
+    check(lib.fftc_candidates(n, flat, lens, 12, ctypes.byref(cnt)), "fftc_candidates")
+    return [list(flat[i * 16:i * 16 + lens[i]]) for i in range(min(cnt.value, 12))]
+
+
+def compiled_lists(dtype="c64"):
+    """(n, radix list) of every specialised kernel compiled for dtype."""
+    code = dtype_code(dtype)
+    out = []
+    for i in range(lib.fftc_compiled_count(code)):
+        n = _i64()
+        arr = (_int * 16)()
+        cnt = _int()
+        check(lib.fftc_compiled_entry(code, i, ctypes.byref(n), arr, 16, ctypes.byref(cnt)),
+              "fftc_compiled_entry")
+        out.append((n.value, list(arr[:cnt.value])))
+    return out
 
 
 def max_single_n(dtype="c64") -> int:

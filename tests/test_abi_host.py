@@ -100,3 +100,24 @@ def test_bad_arguments_rejected_on_host():
     # NULL plan
     assert fftc.lib.fftc_execute(None, None, None, None) == 1
     assert fftc.lib.fftc_destroy_plan(None) == 0
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_compiled_lists_are_valid_factorisations(dtype):
+    lists = fftc.compiled_lists(dtype)
+    assert len(lists) > 100
+    seen = set()
+    for n, rs in lists:
+        assert int(np.prod(rs)) == n and all(r in (2, 3, 4, 5, 7, 8, 16) for r in rs)
+        assert (n, tuple(rs)) not in seen
+        seen.add((n, tuple(rs)))
+    # every length of the mixed-size workload has its preferred list compiled
+    from paper_2207_06803_amd import synth
+    for n in synth.mixed_size_set():
+        assert (n, tuple(fftc.candidates(n)[0])) in seen, n
+
+
+def test_compiled_lists_multiply_to_dft_small():
+    for n, rs in fftc.compiled_lists("c64"):
+        if n <= 128:
+            assert np.abs(F.stockham_product(n, rs) - F.dft_matrix(n)).max() < 1e-11, (n, rs)

@@ -1,0 +1,127 @@
+"""Mixed-length persistent plans and the autotuner on the GPU."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import np_dtype, rel_l2, say, tol_for
+from paper_2207_06803_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2207_06803_amd import fftc  # noqa: E402
+
+
+def pack(xs, dtype):
+    return np.concatenate([x.reshape(-1) for x in xs]).astype(np_dtype(dtype))
+
+
+def check_mixed_output(lengths, x_flat, y_flat, direction, dtype):
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    lengths = np.asarray(lengths)
+    for n in np.unique(lengths):
+        idx = np.nonzero(lengths == n)[0]
+        xs = np.stack([x_flat[offs[i]:offs[i] + n] for i in idx])
+        ys = np.stack([y_flat[offs[i]:offs[i] + n] for i in idx])
+        err = rel_l2(ys, oracle.dft(xs, direction))
+        assert err.max() <= tol_for(n, dtype), (n, err.max())
+
+
+def run(plan, x_np):
+    x = torch.from_numpy(x_np).to("cuda")
+    y = torch.empty_like(x)
+    plan.execute(x, y)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def test_uneven_batch_10000_full_oracle():
+    # 10,000 complex64 transforms, lengths drawn uniformly over the 37-member
+    # set (powers of two 8..4096 and 3, 5, 7 times powers of two up to 3584)
+    g = synth.rng(2)
+    lengths = synth.draw_mixed_sizes(g, 10000)
+    x = synth.uniform_complex(g, (int(lengths.sum()),), np.complex64)
+    say("mixed 10000 transforms, elements", int(lengths.sum()))
+    with fftc.plan_mixed(lengths, fftc.FORWARD, "c64") as p:
+        d = p.describe()
+        assert d["variant"] == "mixed_persistent" and d["mixed_transforms"] == 10000
+        assert d["mixed_classes"] == len(np.unique(lengths))
+        y = run(p, x)
+        y2 = run(p, x)
+    assert np.array_equal(y.view(np.uint32), y2.view(np.uint32))
+    check_mixed_output(lengths, x, y, fftc.FORWARD, "c64")
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("direction", [fftc.FORWARD, fftc.INVERSE])
+def test_mixed_small_list(dtype, direction):
+    g = synth.rng(96, 0 if dtype == "c64" else 1, direction + 1)
+    lengths = np.r_[synth.draw_mixed_sizes(g, 300), [1, 2, 3, 4, 5, 7, 9, 4096, 1, 16]]
+    x = synth.uniform_complex(g, (int(lengths.sum()),), np_dtype(dtype))
+    with fftc.plan_mixed(lengths, direction, dtype) as p:
+        y = run(p, x)
+    check_mixed_output(lengths, x, y, direction, dtype)
+
+
+def test_mixed_equals_per_length_plans():
+    g = synth.rng(97)
+    lengths = synth.draw_mixed_sizes(g, 500)
+    x = synth.uniform_complex(g, (int(lengths.sum()),), np.complex64)
+    with fftc.plan_mixed(lengths) as p:
+        y = run(p, x)
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    for n in np.unique(lengths):
+        idx = np.nonzero(lengths == n)[0]
+        xs = np.stack([x[offs[i]:offs[i] + n] for i in idx])
+        with fftc.Plan(int(n), len(idx)) as q:
+            xd = torch.from_numpy(xs).to("cuda")
+            yd = torch.empty_like(xd)
+            q.execute(xd, yd)
+            torch.cuda.synchronize()
+        ys = np.stack([y[offs[i]:offs[i] + n] for i in idx])
+        # same algorithm and twiddles; allow last-bit differences from code
+        # generation (fused multiply-adds)
+        assert rel_l2(ys, yd.cpu().numpy()).max() <= 1e-6, n
+
+
+def test_graph_replays_and_pointer_changes():
+    g = synth.rng(98)
+    lengths = synth.draw_mixed_sizes(g, 2000)
+    tot = int(lengths.sum())
+    xa = synth.uniform_complex(g, (tot,), np.complex64)
+    xb = synth.uniform_complex(g, (tot,), np.complex64)
+    with fftc.plan_mixed(lengths) as p:
+        da, db = torch.from_numpy(xa).to("cuda"), torch.from_numpy(xb).to("cuda")
+        ya, yb = torch.empty_like(da), torch.empty_like(db)
+        p.execute(da, ya)
+        torch.cuda.synchronize()
+        ref_a = ya.cpu().numpy()
+        for rep in range(4):
+            # eager work and synchronisation between replays
+            scratch = (da * 2).sum()
+            torch.cuda.synchronize()
+            yb.zero_()
+            p.execute(db, yb)      # pointer change -> graph parameters updated
+            ya.zero_()
+            p.execute(da, ya)      # and back
+            torch.cuda.synchronize()
+            assert np.array_equal(ya.cpu().numpy(), ref_a), rep
+            del scratch
+        check_mixed_output(lengths, xb, yb.cpu().numpy(), fftc.FORWARD, "c64")
+
+
+def test_autotune_records_choice():
+    fftc.tune_clear()
+    try:
+        for n in (1024, 3584, 64):
+            rs, us = fftc.autotune(n, (1 << 20) // n, "c64", reps=5)
+            say(f"autotune n={n} -> {rs} {us:.2f} us")
+            assert int(np.prod(rs)) == n and us > 0
+            assert fftc.factorize(n)[0] == rs
+            with fftc.Plan(n, 8) as p:
+                assert p.describe()["radices"] == rs
+    finally:
+        fftc.tune_clear()

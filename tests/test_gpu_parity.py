@@ -38,21 +38,6 @@ def test_config1_n64_batch1024_full():
     say("config1 max rel L2", err.max(), desc["variant"], desc["radices"])
 
 
-SPEC_C64 = [(8, [8]), (16, [16]), (32, [2, 16]), (32, [16, 2]), (32, [4, 8]), (32, [8, 4]),
-            (64, [4, 16]), (64, [16, 4]), (64, [8, 8]), (128, [8, 16]), (128, [16, 8]),
-            (256, [16, 16]), (256, [4, 4, 16]), (512, [8, 8, 8]), (512, [2, 16, 16]),
-            (512, [16, 16, 2]), (1024, [4, 16, 16]), (1024, [16, 16, 4]), (1024, [16, 4, 16]),
-            (1024, [8, 8, 16]), (2048, [8, 16, 16]), (2048, [16, 16, 8]), (4096, [16, 16, 16]),
-            (4096, [8, 8, 8, 8]), (4096, [4, 16, 4, 16]), (8192, [2, 16, 16, 16]),
-            (8192, [16, 16, 16, 2]), (8192, [8, 16, 8, 8]), (16384, [4, 16, 16, 16]),
-            (16384, [16, 16, 16, 4])]
-SPEC_C128 = [(8, [8]), (16, [16]), (32, [2, 16]), (32, [8, 4]), (64, [4, 16]), (64, [8, 8]),
-             (128, [8, 16]), (128, [16, 8]), (256, [16, 16]), (256, [4, 4, 16]), (512, [8, 8, 8]),
-             (512, [2, 16, 16]), (1024, [4, 16, 16]), (1024, [16, 16, 4]), (1024, [8, 8, 16]),
-             (2048, [8, 16, 16]), (2048, [16, 16, 8]), (4096, [16, 16, 16]), (4096, [8, 8, 8, 8]),
-             (8192, [2, 16, 16, 16]), (8192, [16, 16, 16, 2])]
-
-
 def _ragged_batch(n):
     # several workgroups and a partial last one
     per = max(1, 256 // max(1, n // 16))
@@ -62,18 +47,22 @@ def _ragged_batch(n):
     return b
 
 
-@pytest.mark.parametrize("n,rs", SPEC_C64, ids=lambda v: str(v))
-def test_specialised_c64(n, rs):
-    for d in (FWD, INV):
-        _, desc = check(n, _ragged_batch(n), d, "c64", radices=rs)
-        assert desc["variant"] == "single_specialised", desc
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_every_compiled_list(dtype):
+    # every specialised kernel, both directions, several groups + ragged tail
+    lists = fftc.compiled_lists(dtype)
+    assert len(lists) > 100
+    for n, rs in lists:
+        for d in (FWD, INV):
+            _, desc = check(n, _ragged_batch(n), d, dtype, radices=rs)
+            assert desc["variant"] == "single_specialised", desc
 
 
-@pytest.mark.parametrize("n,rs", SPEC_C128, ids=lambda v: str(v))
-def test_specialised_c128(n, rs):
-    for d in (FWD, INV):
-        _, desc = check(n, _ragged_batch(n), d, "c128", radices=rs)
-        assert desc["variant"] == "single_specialised", desc
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_default_plans_are_compiled(dtype):
+    for n in [1 << k for k in range(3, 14)] + synth.mixed_size_set():
+        with fftc.Plan(n, 4, FWD, dtype) as p:
+            assert p.describe()["variant"] == "single_specialised", (n, p.describe())
 
 
 GENERIC_C64 = [(12, [4, 3]), (12, [3, 4]), (3072, [3, 4, 16, 16]), (3584, [7, 8, 8, 8]),
