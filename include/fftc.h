@@ -49,7 +49,17 @@ enum { FFTC_FORWARD = -1, FFTC_INVERSE = +1 };
 /* Element type and arithmetic of a plan. */
 enum {
     FFTC_C64 = 0,  /* complex64 in and out, fp32 arithmetic, twiddles made in fp64 */
-    FFTC_C128 = 1  /* complex128 in and out, fp64 arithmetic */
+    FFTC_C128 = 1, /* complex128 in and out, fp64 arithmetic */
+    /* complex64 in and out; every DFT_16 stage is a dense 16 x 16 complex
+     * product on the matrix cores with split low-precision operands and fp32
+     * accumulation (x = x_hi + 2^-s x_lo, products hi*hi + 2^-s (hi*lo +
+     * lo*hi)); twiddles and any radix-2/4/8 stage in fp32.  Lengths 256,
+     * 512, 1024, 2048, 4096, 8192, 16384.  Intermediate values must stay
+     * within the fp16 range for the fp16 modes (|y| < 65504). */
+    FFTC_C64_SPLIT_F16 = 2,   /* fp16 hi + lo, s = 11 */
+    FFTC_C64_SPLIT_BF16 = 3,  /* bf16 hi + lo, s = 8 */
+    FFTC_C64_SPLIT3_BF16 = 4, /* bf16 hi + mid + lo, three-term products */
+    FFTC_C64_F16 = 5          /* fp16 operands without split (reference) */
 };
 
 /* Plan variants reported by fftc_plan_describe. */
@@ -57,14 +67,16 @@ enum {
     FFTC_VARIANT_SINGLE_SPECIALISED = 0, /* one kernel compiled for this N and radix list */
     FFTC_VARIANT_SINGLE_GENERIC = 1,     /* one kernel, runtime N and radix list */
     FFTC_VARIANT_TWO_PASS = 2,           /* Eq. 2 four-step in two kernels + scratch */
-    FFTC_VARIANT_MIXED_PERSISTENT = 3    /* mixed lengths, one persistent launch in a hipGraph */
+    FFTC_VARIANT_MIXED_PERSISTENT = 3,   /* mixed lengths, one persistent launch in a hipGraph */
+    FFTC_VARIANT_SPLIT_MFMA = 4          /* DFT_16 stages on the matrix cores (split precision) */
 };
 
 typedef struct fftc_plan_s *fftc_plan_t;
 
 /*
  * Create a plan for `batch` transforms of length `n`.
- *   direction: FFTC_FORWARD or FFTC_INVERSE;  dtype: FFTC_C64 or FFTC_C128.
+ *   direction: FFTC_FORWARD or FFTC_INVERSE;  dtype: one of FFTC_C64,
+ *   FFTC_C128 or the split-precision complex64 modes above.
  * The radix list comes from the tuning database when it holds an entry for
  * (n, dtype), else from the built-in heuristic.  Allocates the plan's twiddle
  * tables (generated in fp64 on the GPU of the current device) and, for

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "plan.h"
+#include "split16.h"
 
 namespace fftc {
 
@@ -42,7 +43,7 @@ const SpecEntry* find_spec(int dtype, int64_t n, const std::vector<int>& rs) {
     return nullptr;
 }
 
-static size_t csize_of(int dtype) { return dtype == FFTC_C128 ? 16 : 8; }
+static size_t csize_of(int dtype) { return dtype == FFTC_C128 ? 16 : 8; }  // split modes: complex64
 
 static fftc_status check_radices(int64_t n, const std::vector<int>& rs) {
     int64_t prod = 1;
@@ -91,8 +92,15 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
     *out = nullptr;
     if (direction != FFTC_FORWARD && direction != FFTC_INVERSE)
         return fail(FFTC_ERR_INVALID_ARG, "direction must be FFTC_FORWARD (-1) or FFTC_INVERSE (+1)");
-    if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "dtype must be FFTC_C64 or FFTC_C128");
+    if (dtype != FFTC_C64 && dtype != FFTC_C128 && !is_split_dtype(dtype))
+        return fail(FFTC_ERR_INVALID_ARG, "dtype must be FFTC_C64, FFTC_C128 or a split-precision mode");
     if (batch < 1) return fail(FFTC_ERR_INVALID_ARG, "batch must be >= 1");
+    if (is_split_dtype(dtype)) {
+        if (!split_supported(n))
+            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "split-precision plans take n in {256, 512, ..., 16384}");
+        if (radices) return fail(FFTC_ERR_INVALID_ARG, "split-precision plans use their own radix list");
+        if (batch > 0x7fffffff) return fail(FFTC_ERR_INVALID_ARG, "batch too large");
+    }
     if (n < 1 || n > max_total_n(dtype) || !is_7smooth(n))
         return fail(FFTC_ERR_UNSUPPORTED_SIZE,
                     "n = " + std::to_string(n) + " unsupported (need 1 <= n <= 2^20 with prime factors <= 7)");
@@ -117,7 +125,15 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
     hipGetDevice(&p->device);
     const size_t cs = csize_of(dtype);
 
-    if (n <= max_single_n(dtype)) {
+    if (is_split_dtype(dtype)) {
+        p->variant = FFTC_VARIANT_SPLIT_MFMA;
+        p->radices = split_radices(n);
+        p->tpt = split_threads(n);
+        p->t = 1;
+        std::vector<TwSegment> segs;
+        const int64_t entries = stage_segments(p->radices, 0, &segs);
+        st = alloc_tables(p, segs, entries);
+    } else if (n <= max_single_n(dtype)) {
         std::vector<int> rs;
         if (radices) {
             rs.assign(radices, radices + count);
@@ -269,6 +285,7 @@ fftc_status fftc_execute(fftc_plan_t p, const void* in, void* out, void* stream)
         return fail(FFTC_ERR_INVALID_ARG, "in/out not aligned to the complex element size");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p->variant == FFTC_VARIANT_MIXED_PERSISTENT) return launch_mixed(p, in, out, s);
+    if (p->variant == FFTC_VARIANT_SPLIT_MFMA) return launch_split(p, in, out, s);
     if (p->variant == FFTC_VARIANT_TWO_PASS) return launch_two_pass(p, in, out, s);
     return launch_single(p, in, out, s);
 }

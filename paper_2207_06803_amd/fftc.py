@@ -18,9 +18,18 @@ FORWARD = -1
 INVERSE = +1
 C64 = 0
 C128 = 1
-DTYPES = {"c64": C64, "complex64": C64, C64: C64, "c128": C128, "complex128": C128, C128: C128}
+C64_SPLIT_F16 = 2
+C64_SPLIT_BF16 = 3
+C64_SPLIT3_BF16 = 4
+C64_F16 = 5
+DTYPES = {"c64": C64, "complex64": C64, C64: C64, "c128": C128, "complex128": C128, C128: C128,
+          "split_f16": C64_SPLIT_F16, C64_SPLIT_F16: C64_SPLIT_F16,
+          "split_bf16": C64_SPLIT_BF16, C64_SPLIT_BF16: C64_SPLIT_BF16,
+          "split3_bf16": C64_SPLIT3_BF16, C64_SPLIT3_BF16: C64_SPLIT3_BF16,
+          "f16": C64_F16, C64_F16: C64_F16}
 
-VARIANT_NAMES = {0: "single_specialised", 1: "single_generic", 2: "two_pass", 3: "mixed_persistent"}
+VARIANT_NAMES = {0: "single_specialised", 1: "single_generic", 2: "two_pass", 3: "mixed_persistent",
+                 4: "split_mfma"}
 
 STATUS = {0: "FFTC_OK", 1: "FFTC_ERR_INVALID_ARG", 2: "FFTC_ERR_UNSUPPORTED_SIZE",
           3: "FFTC_ERR_OUT_OF_MEMORY", 4: "FFTC_ERR_TOO_LARGE", 5: "FFTC_ERR_HIP",
