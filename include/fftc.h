@@ -102,6 +102,10 @@ fftc_status fftc_plan_radices(int64_t n, int64_t batch, int direction, int dtype
  */
 fftc_status fftc_execute(fftc_plan_t plan, const void *in, void *out, void *stream);
 
+/* As fftc_execute for the first `batch` transforms only (1 <= batch <= the
+ * plan's batch); in and out hold batch * n elements.  Not for mixed plans. */
+fftc_status fftc_execute_batch(fftc_plan_t plan, const void *in, void *out, int64_t batch, void *stream);
+
 /* Free the plan's device memory.  NULL is a no-op.  The caller must ensure
  * no execution of the plan is still in flight. */
 fftc_status fftc_destroy_plan(fftc_plan_t plan);
@@ -186,6 +190,79 @@ fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int *ra
 fftc_status fftc_tune_load(const char *path, int *entries);
 fftc_status fftc_tune_save(const char *path, int *entries);
 fftc_status fftc_tune_clear(void);
+
+/* ---------------------------------------------------------------------------
+ * Serving.  One process-global server takes FFT requests of any supported
+ * length and batch as they arrive and runs them with continuous batching:
+ * requests are admitted in arrival order as device memory (a budget arena
+ * for outputs) and in-flight slots free up, each admitted request is launched
+ * at once on a stream of a pool so it overlaps with work already on the GPU,
+ * and plans with their twiddle tables stay resident between requests.
+ * ------------------------------------------------------------------------- */
+enum { FFTC_EXECUTOR_GPU = 0, FFTC_EXECUTOR_MOCK = 1 };
+
+typedef struct {
+    size_t budget_bytes;   /* device memory for request outputs */
+    int n_streams;         /* HIP streams the requests are spread over (>= 1) */
+    int max_inflight;      /* requests on the GPU at once (>= 1) */
+    int executor;          /* FFTC_EXECUTOR_GPU, or FFTC_EXECUTOR_MOCK: no device
+                              use and no computation, for testing the admission
+                              and scheduling logic on a host without a GPU */
+    int64_t mock_ns_per_mb;/* mock executor: simulated time per MiB of output */
+} fftc_server_config;
+
+typedef struct {
+    int64_t n, batch;      /* batch transforms of length n */
+    int direction, dtype;
+    const void *in;        /* device input, batch * n elements; must stay valid
+                              until the request's completion is polled */
+    uint64_t tag;          /* returned in the completion */
+    int64_t arrival_ns;    /* caller's arrival time on fftc_now_ns's clock */
+} fftc_request;
+
+typedef struct {
+    uint64_t tag;
+    fftc_status status;    /* FFTC_OK, FFTC_ERR_SHUTDOWN (cancelled) or a launch error */
+    void *out;             /* device output (batch * n elements) owned by the
+                              caller until fftc_release; NULL unless OK */
+    int64_t arrival_ns, admit_ns, start_ns, done_ns;  /* done: completion observed */
+    int64_t n, batch;
+} fftc_completion;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected, cancelled, failed;
+    size_t budget_bytes, bytes_in_use, peak_bytes;
+    int pending, inflight, max_inflight_seen;
+} fftc_server_stats;
+
+/* Monotonic clock (ns) used for all server timestamps. */
+int64_t fftc_now_ns(void);
+
+/* Start the server on the current device: allocates the budget arena, the
+ * streams and events.  Fails if a server is already running. */
+fftc_status fftc_server_start(const fftc_server_config *cfg);
+
+/* Build (and keep) the plan for (n, direction, dtype) able to run batches up
+ * to max_batch, so the first request of that shape pays no planning cost. */
+fftc_status fftc_server_prepare(int64_t n, int direction, int dtype, int64_t max_batch);
+
+/* Queue a request (copied); returns at once.  FFTC_ERR_TOO_LARGE if its
+ * output alone exceeds the budget; a full arena only delays admission. */
+fftc_status fftc_submit(const fftc_request *req);
+
+/* Take up to max finished requests (non-blocking); *n_out = how many. */
+fftc_status fftc_poll(fftc_completion *out, int max, int *n_out);
+
+/* Return a completion's output to the arena. */
+fftc_status fftc_release(void *out);
+
+fftc_status fftc_server_stats_get(fftc_server_stats *stats);
+
+/* Stop: drain != 0 runs everything queued first (outputs still have to be
+ * released by the caller if memory is short), else queued requests complete
+ * with FFTC_ERR_SHUTDOWN.  Waits for GPU work, then frees plans, arena and
+ * streams (outputs not yet released become invalid). */
+fftc_status fftc_server_stop(int drain);
 
 /* Text of a status code (static storage). */
 const char *fftc_status_string(fftc_status s);

@@ -12,6 +12,8 @@
 namespace fftc {
 
 static thread_local std::string t_last_error;
+// Set by the server while it builds plans it only runs out of place.
+thread_local bool t_plan_no_scratch = false;
 
 fftc_status fail(fftc_status s, const std::string& msg) {
     t_last_error = msg;
@@ -181,7 +183,7 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
                 p->t = tc;
                 st = alloc_tables(p, segs, p->twn_off + n);
             }
-            if (st == FFTC_OK) {
+            if (st == FFTC_OK && !t_plan_no_scratch) {
                 p->scratch_bytes = (size_t)batch * (size_t)n * cs;
                 hipError_t e = hipMalloc(&p->scratch, p->scratch_bytes);
                 if (e != hipSuccess) st = fail_hip(e, "hipMalloc(two-pass scratch)");
@@ -276,7 +278,7 @@ fftc_status fftc_plan_mixed(const int64_t* n, int64_t count, int direction, int 
     }
 }
 
-fftc_status fftc_execute(fftc_plan_t p, const void* in, void* out, void* stream) {
+static fftc_status execute_impl(fftc_plan_t p, const void* in, void* out, int64_t batch, void* stream) {
     clear_error();
     if (!p) return fail(FFTC_ERR_INVALID_ARG, "plan is NULL");
     if (!in || !out) return fail(FFTC_ERR_INVALID_ARG, "in/out is NULL");
@@ -284,10 +286,22 @@ fftc_status fftc_execute(fftc_plan_t p, const void* in, void* out, void* stream)
     if (((uintptr_t)in % align) || ((uintptr_t)out % align))
         return fail(FFTC_ERR_INVALID_ARG, "in/out not aligned to the complex element size");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (p->variant == FFTC_VARIANT_MIXED_PERSISTENT) return launch_mixed(p, in, out, s);
-    if (p->variant == FFTC_VARIANT_SPLIT_MFMA) return launch_split(p, in, out, s);
-    if (p->variant == FFTC_VARIANT_TWO_PASS) return launch_two_pass(p, in, out, s);
-    return launch_single(p, in, out, s);
+    if (p->variant == FFTC_VARIANT_MIXED_PERSISTENT) {
+        if (batch != p->batch) return fail(FFTC_ERR_INVALID_ARG, "mixed plans run their whole list");
+        return launch_mixed(p, in, out, s);
+    }
+    if (batch < 1 || batch > p->batch) return fail(FFTC_ERR_INVALID_ARG, "batch must be in [1, plan batch]");
+    if (p->variant == FFTC_VARIANT_SPLIT_MFMA) return launch_split(p, in, out, batch, s);
+    if (p->variant == FFTC_VARIANT_TWO_PASS) return launch_two_pass(p, in, out, batch, s);
+    return launch_single(p, in, out, batch, s);
+}
+
+fftc_status fftc_execute(fftc_plan_t p, const void* in, void* out, void* stream) {
+    return execute_impl(p, in, out, p ? p->batch : 0, stream);
+}
+
+fftc_status fftc_execute_batch(fftc_plan_t p, const void* in, void* out, int64_t batch, void* stream) {
+    return execute_impl(p, in, out, batch, stream);
 }
 
 fftc_status fftc_destroy_plan(fftc_plan_t p) {

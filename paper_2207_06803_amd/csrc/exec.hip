@@ -117,12 +117,12 @@ void fill_gen_desc(int64_t n, const std::vector<int>& rs, int tpt, int t, int64_
 static uint32_t mul_for(int d) { return d > 1 ? (uint32_t)(((uint64_t(1) << 32) + d - 1) / d) : 0u; }
 
 template <typename Real>
-static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
+static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* out, int64_t batch,
+                                   hipStream_t s) {
     using C = cplx<Real>;
     const C* tin = static_cast<const C*>(in);
     C* tout = static_cast<C*>(out);
     const C* tw = static_cast<const C*>(p->tw);
-    int64_t batch = p->batch;
     const bool inv = p->direction == FFTC_INVERSE;
     if (p->spec) {
         const int64_t groups = (batch + p->spec->t - 1) / p->spec->t;
@@ -151,9 +151,9 @@ static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* o
     return FFTC_OK;
 }
 
-fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
-    return p->dtype == FFTC_C128 ? launch_single_t<double>(p, in, out, s)
-                                 : launch_single_t<float>(p, in, out, s);
+fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s) {
+    return p->dtype == FFTC_C128 ? launch_single_t<double>(p, in, out, batch, s)
+                                 : launch_single_t<float>(p, in, out, batch, s);
 }
 
 // Columns per workgroup in a two-pass plan: 128 contiguous bytes per access.
@@ -165,7 +165,8 @@ static fftc_status launch_two_pass_chunk(const fftc_plan_s* p, const cplx<Real>*
                                          int tc, size_t csz, int64_t nb, hipStream_t s);
 
 template <typename Real, bool INV>
-static fftc_status launch_two_pass_t(const fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
+static fftc_status launch_two_pass_t(const fftc_plan_s* p, const void* in, void* out, int64_t batch,
+                                     hipStream_t s) {
     using C = cplx<Real>;
     const C* tin = static_cast<const C*>(in);
     C* tout = static_cast<C*>(out);
@@ -177,8 +178,8 @@ static fftc_status launch_two_pass_t(const fftc_plan_s* p, const void* in, void*
     const size_t csz = sizeof(C);
     // grid.y carries the transform index; split very large batches
     constexpr int64_t kMaxY = 65535;
-    for (int64_t b0 = 0; b0 < p->batch; b0 += kMaxY) {
-        const int64_t nb = std::min<int64_t>(kMaxY, p->batch - b0);
+    for (int64_t b0 = 0; b0 < batch; b0 += kMaxY) {
+        const int64_t nb = std::min<int64_t>(kMaxY, batch - b0);
         const int64_t o = b0 * p->n;
         fftc_status st = launch_two_pass_chunk<Real, INV>(p, tin + o, mid + o, tout + o, tw, twn, tc, csz, nb, s);
         if (st != FFTC_OK) return st;
@@ -212,11 +213,14 @@ static fftc_status launch_two_pass_chunk(const fftc_plan_s* p, const cplx<Real>*
     return FFTC_OK;
 }
 
-fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
+fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s) {
     const bool inv = p->direction == FFTC_INVERSE;
+    if (in == out && !p->scratch) return fail(FFTC_ERR_INVALID_ARG, "this two-pass plan has no scratch for in-place use");
     if (p->dtype == FFTC_C128)
-        return inv ? launch_two_pass_t<double, true>(p, in, out, s) : launch_two_pass_t<double, false>(p, in, out, s);
-    return inv ? launch_two_pass_t<float, true>(p, in, out, s) : launch_two_pass_t<float, false>(p, in, out, s);
+        return inv ? launch_two_pass_t<double, true>(p, in, out, batch, s)
+                   : launch_two_pass_t<double, false>(p, in, out, batch, s);
+    return inv ? launch_two_pass_t<float, true>(p, in, out, batch, s)
+               : launch_two_pass_t<float, false>(p, in, out, batch, s);
 }
 
 // Allow the dynamic-LDS kernels to use up to the gfx950 per-group maximum.

@@ -24,7 +24,7 @@ struct fftc_plan_s {
     fftc::GenDesc pass1{}, pass2{};  // length m (k columns), length k (m columns)
     std::vector<int> r1, r2;
     int64_t tw1_off = 0, tw2_off = 0, twn_off = 0;  // table offsets (elements)
-    void* scratch = nullptr;
+    void* scratch = nullptr;  // two-pass in-place intermediate (absent: in place refused)
     size_t scratch_bytes = 0;
     // mixed-length persistent plan
     fftc::MixedState* mixed = nullptr;
@@ -32,8 +32,9 @@ struct fftc_plan_s {
 
 namespace fftc {
 
-fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, hipStream_t s);
-fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, hipStream_t s);
+// `batch` <= p->batch: run the first `batch` transforms.
+fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);
+fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);
 fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count);
 fftc_status launch_mixed(fftc_plan_s* p, const void* in, void* out, hipStream_t s);
 void destroy_mixed(MixedState* m);

@@ -1,0 +1,512 @@
+// Serving runtime: FFT requests of different lengths and batch sizes are
+// taken as they arrive and run with continuous batching on one GPU.
+//
+//  - Plans (and their twiddle tables) stay resident, one per (n, direction,
+//    dtype), sized for the largest batch seen; requests run the first `batch`
+//    transforms of the plan.
+//  - Outputs come from one device arena of `budget_bytes` (first fit with
+//    coalescing, 256-byte granules).  A request is admitted in arrival order
+//    when its output fits in the free arena and an in-flight slot is free;
+//    otherwise it -- and everything behind it -- waits (FIFO, so no request
+//    starves).  A request larger than the whole budget is refused at submit.
+//  - Each admitted request is launched at once on the next stream of a pool,
+//    so work admitted while earlier requests are still on the GPU overlaps
+//    with them; an event per request marks its completion, which the
+//    dispatcher observes and publishes with arrival / admit / start / done
+//    timestamps.  The output stays owned by the client until fftc_release.
+//  - A host-only mock executor (no HIP calls, no computation) replaces the
+//    device for testing admission and scheduling on a CPU.
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "plan.h"
+#include "split16.h"
+
+namespace fftc {
+
+extern thread_local bool t_plan_no_scratch;
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+namespace {
+
+constexpr size_t kGranule = 256;
+
+// First-fit allocator over [0, cap) with coalescing of free neighbours.
+class Arena {
+   public:
+    void reset(size_t cap) {
+        cap_ = cap;
+        free_.clear();
+        if (cap) free_[0] = cap;
+        used_ = peak_ = 0;
+    }
+    bool alloc(size_t sz, size_t* off) {
+        sz = round(sz);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= sz) {
+                *off = it->first;
+                const size_t rest = it->second - sz;
+                const size_t at = it->first + sz;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += sz;
+                peak_ = std::max(peak_, used_);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t sz) {
+        sz = round(sz);
+        used_ -= sz;
+        auto it = free_.emplace(off, sz).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+    size_t cap() const { return cap_; }
+    static size_t round(size_t s) { return (s + kGranule - 1) / kGranule * kGranule; }
+
+   private:
+    size_t cap_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;
+};
+
+struct Pending {
+    fftc_request r;
+    size_t bytes;
+};
+
+struct InFlight {
+    Pending q;
+    size_t off;
+    void* out;
+    int64_t admit_ns, start_ns, mock_done_ns;
+    hipEvent_t ev;
+    fftc_status status;
+};
+
+size_t elem_bytes(int dtype) { return dtype == FFTC_C128 ? 16 : 8; }
+
+class Server {
+   public:
+    fftc_status start(const fftc_server_config& cfg) {
+        cfg_ = cfg;
+        mock_ = cfg.executor == FFTC_EXECUTOR_MOCK;
+        if (cfg_.n_streams < 1) cfg_.n_streams = 1;
+        if (cfg_.max_inflight < 1) cfg_.max_inflight = 1;
+        arena_.reset(cfg.budget_bytes / kGranule * kGranule);
+        stats_ = fftc_server_stats{};
+        stats_.budget_bytes = arena_.cap();
+        if (!mock_) {
+            FFTC_HIP_TRY(hipGetDevice(&device_));
+            FFTC_HIP_TRY(hipMalloc(&base_, std::max<size_t>(arena_.cap(), kGranule)));
+            streams_.resize(cfg_.n_streams);
+            for (auto& s : streams_) FFTC_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            for (int i = 0; i < cfg_.max_inflight; ++i) {
+                hipEvent_t e;
+                FFTC_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                events_.push_back(e);
+            }
+        } else {
+            base_ = reinterpret_cast<void*>(uintptr_t(1) << 40);  // fake, never dereferenced
+        }
+        stop_ = false;
+        drain_ = true;
+        th_ = std::thread([this] { loop(); });
+        return FFTC_OK;
+    }
+
+    fftc_status prepare(int64_t n, int direction, int dtype, int64_t max_batch) {
+        std::lock_guard<std::mutex> g(plan_mu_);
+        fftc_plan_t p = nullptr;
+        return get_plan(n, direction, dtype, max_batch, &p);
+    }
+
+    fftc_status submit(const fftc_request& r) {
+        if (r.n < 1 || r.batch < 1 || !r.in) return fail(FFTC_ERR_INVALID_ARG, "bad request (n, batch, in)");
+        if (r.direction != FFTC_FORWARD && r.direction != FFTC_INVERSE) return fail(FFTC_ERR_INVALID_ARG, "bad direction");
+        if (r.dtype != FFTC_C64 && r.dtype != FFTC_C128 && !is_split_dtype(r.dtype))
+            return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
+        if (!is_7smooth(r.n) || r.n > max_total_n(r.dtype)) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "unsupported n");
+        const size_t bytes = Arena::round((size_t)r.n * (size_t)r.batch * elem_bytes(r.dtype));
+        std::lock_guard<std::mutex> g(mu_);
+        if (stop_) return fail(FFTC_ERR_SHUTDOWN, "server is stopping");
+        if (bytes > arena_.cap()) {
+            ++stats_.rejected;
+            return fail(FFTC_ERR_TOO_LARGE, "request output exceeds the memory budget");
+        }
+        incoming_.push_back(Pending{r, bytes});
+        ++stats_.submitted;
+        cv_.notify_one();
+        return FFTC_OK;
+    }
+
+    int poll(fftc_completion* out, int max) {
+        std::lock_guard<std::mutex> g(mu_);
+        int k = 0;
+        while (k < max && !done_.empty()) {
+            out[k++] = done_.front();
+            done_.pop_front();
+        }
+        return k;
+    }
+
+    fftc_status release(void* out) {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = live_.find(out);
+        if (it == live_.end()) return fail(FFTC_ERR_INVALID_ARG, "pointer is not a live server output");
+        arena_.release(it->second.first, it->second.second);
+        live_.erase(it);
+        stats_.bytes_in_use = arena_.used();
+        cv_.notify_one();
+        return FFTC_OK;
+    }
+
+    // Stop taking requests; with drain, queued requests still run (their
+    // outputs must be released by the client meanwhile if memory is short),
+    // else they complete with FFTC_ERR_SHUTDOWN.  Waits for the GPU work.
+    fftc_status stop(bool drain) {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+            drain_ = drain;
+            cv_.notify_one();
+        }
+        if (th_.joinable()) th_.join();
+        fftc_status st = FFTC_OK;
+        {
+            std::lock_guard<std::mutex> g(plan_mu_);
+            for (auto& kv : plans_) fftc_destroy_plan(kv.second);
+            for (auto p : retired_) fftc_destroy_plan(p);
+            plans_.clear();
+            retired_.clear();
+        }
+        if (!mock_) {
+            for (auto e : events_) hipEventDestroy(e);
+            for (auto s : streams_) hipStreamDestroy(s);
+            if (base_ && hipFree(base_) != hipSuccess) st = fail(FFTC_ERR_HIP, "hipFree(arena)");
+        }
+        events_.clear();
+        streams_.clear();
+        base_ = nullptr;
+        live_.clear();
+        return st;
+    }
+
+    void stats(fftc_server_stats* s) {
+        std::lock_guard<std::mutex> g(mu_);
+        stats_.bytes_in_use = arena_.used();
+        stats_.peak_bytes = arena_.peak();
+        stats_.pending = (int)(incoming_.size() + pending_.size());
+        stats_.inflight = running_count_;
+        *s = stats_;
+    }
+
+   private:
+    // plan cache; plan_mu_ held
+    fftc_status get_plan(int64_t n, int direction, int dtype, int64_t batch, fftc_plan_t* out) {
+        const auto key = std::make_tuple(n, direction, dtype);
+        auto it = plans_.find(key);
+        if (it != plans_.end() && it->second->batch >= batch) {
+            *out = it->second;
+            return FFTC_OK;
+        }
+        const int64_t cap = std::max<int64_t>(batch, it != plans_.end() ? it->second->batch : 0);
+        fftc_plan_t p = nullptr;
+        t_plan_no_scratch = true;  // the server never runs in place
+        fftc_status st = fftc_plan(n, std::max<int64_t>(cap, 1), direction, dtype, &p);
+        t_plan_no_scratch = false;
+        if (st != FFTC_OK) return st;
+        if (it != plans_.end()) {
+            retired_.push_back(it->second);  // may still be in flight; freed at stop
+            it->second = p;
+        } else {
+            plans_[key] = p;
+        }
+        *out = p;
+        return FFTC_OK;
+    }
+
+    // mu_ held by caller for state; launches outside the lock are fine since
+    // only this thread touches streams, events and plans
+    fftc_status launch(InFlight& f, int slot) {
+        f.start_ns = now_ns();
+        if (mock_) {
+            const double mb = (double)f.q.bytes / (1 << 20);
+            f.mock_done_ns = f.start_ns + (int64_t)(cfg_.mock_ns_per_mb * mb);
+            return FFTC_OK;
+        }
+        fftc_plan_t p = nullptr;
+        {
+            std::lock_guard<std::mutex> g(plan_mu_);
+            fftc_status st = get_plan(f.q.r.n, f.q.r.direction, f.q.r.dtype, f.q.r.batch, &p);
+            if (st != FFTC_OK) return st;
+        }
+        hipStream_t s = streams_[next_stream_];
+        next_stream_ = (next_stream_ + 1) % (int)streams_.size();
+        fftc_status st = fftc_execute_batch(p, f.q.r.in, f.out, f.q.r.batch, s);
+        if (st != FFTC_OK) return st;
+        f.ev = events_[slot];
+        hipError_t e = hipEventRecord(f.ev, s);
+        if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
+        return FFTC_OK;
+    }
+
+    bool finished(InFlight& f) {
+        if (f.status != FFTC_OK) return true;
+        if (mock_) return now_ns() >= f.mock_done_ns;
+        hipError_t e = hipEventQuery(f.ev);
+        if (e == hipErrorNotReady) return false;
+        if (e != hipSuccess) f.status = FFTC_ERR_HIP;
+        return true;
+    }
+
+    void loop() {
+        if (!mock_) hipSetDevice(device_);
+        std::vector<int> free_slots;
+        for (int i = cfg_.max_inflight - 1; i >= 0; --i) free_slots.push_back(i);
+        std::vector<std::pair<InFlight, int>> running;
+        for (;;) {
+            bool progressed = false;
+            std::vector<std::pair<InFlight, int>> to_launch;
+            bool stopping, drain;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                while (!incoming_.empty()) {
+                    pending_.push_back(incoming_.front());
+                    incoming_.pop_front();
+                }
+                stopping = stop_;
+                drain = drain_;
+                if (stopping && !drain) {
+                    for (auto& q : pending_) {
+                        fftc_completion c{};
+                        c.tag = q.r.tag;
+                        c.status = FFTC_ERR_SHUTDOWN;
+                        c.arrival_ns = q.r.arrival_ns;
+                        c.done_ns = now_ns();
+                        done_.push_back(c);
+                        ++stats_.cancelled;
+                    }
+                    pending_.clear();
+                }
+                // admission in arrival order: the head waits for room
+                while (!pending_.empty() && !free_slots.empty()) {
+                    size_t off = 0;
+                    if (!arena_.alloc(pending_.front().bytes, &off)) break;
+                    InFlight f{};
+                    f.q = pending_.front();
+                    pending_.pop_front();
+                    f.off = off;
+                    f.out = static_cast<char*>(base_) + off;
+                    f.admit_ns = now_ns();
+                    f.status = FFTC_OK;
+                    live_[f.out] = {off, f.q.bytes};
+                    to_launch.emplace_back(f, free_slots.back());
+                    free_slots.pop_back();
+                    ++stats_.admitted;
+                }
+                running_count_ = (int)(running.size() + to_launch.size());
+                stats_.max_inflight_seen = std::max<int>(stats_.max_inflight_seen, running_count_);
+            }
+            for (auto& fl : to_launch) {
+                fl.first.status = launch(fl.first, fl.second);
+                running.push_back(fl);
+                progressed = true;
+            }
+            // completions
+            std::vector<fftc_completion> fin;
+            std::vector<void*> failed_out;
+            for (size_t i = 0; i < running.size();) {
+                if (finished(running[i].first)) {
+                    InFlight& f = running[i].first;
+                    fftc_completion c{};
+                    c.tag = f.q.r.tag;
+                    c.status = f.status;
+                    c.out = f.status == FFTC_OK ? f.out : nullptr;
+                    c.arrival_ns = f.q.r.arrival_ns;
+                    c.admit_ns = f.admit_ns;
+                    c.start_ns = f.start_ns;
+                    c.done_ns = now_ns();
+                    c.n = f.q.r.n;
+                    c.batch = f.q.r.batch;
+                    if (f.status != FFTC_OK) failed_out.push_back(f.out);
+                    fin.push_back(c);
+                    free_slots.push_back(running[i].second);
+                    running[i] = running.back();
+                    running.pop_back();
+                    progressed = true;
+                } else {
+                    ++i;
+                }
+            }
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                for (void* o : failed_out) {  // a failed launch gives its output back
+                    auto it = live_.find(o);
+                    if (it != live_.end()) {
+                        arena_.release(it->second.first, it->second.second);
+                        live_.erase(it);
+                    }
+                }
+                for (auto& c : fin) {
+                    done_.push_back(c);
+                    ++stats_.completed;
+                    if (c.status != FFTC_OK) ++stats_.failed;
+                }
+                running_count_ = (int)running.size();
+                if (stop_ && running.empty() && incoming_.empty() && pending_.empty()) break;
+                // idle, or the queue head waits for memory or a slot: sleep
+                // until a submit, release or stop (or a short timeout)
+                if (!progressed && running.empty()) cv_.wait_for(lk, std::chrono::milliseconds(2));
+            }
+            // work on the GPU: poll its events without a timed sleep
+            if (!progressed && !running.empty()) std::this_thread::yield();
+        }
+    }
+
+    fftc_server_config cfg_{};
+    bool mock_ = false;
+    int device_ = 0;
+    void* base_ = nullptr;
+    Arena arena_;
+    std::vector<hipStream_t> streams_;
+    std::vector<hipEvent_t> events_;
+    int next_stream_ = 0;
+    std::thread th_;
+    std::mutex mu_, plan_mu_;
+    std::condition_variable cv_;
+    bool stop_ = false, drain_ = true;
+    std::deque<Pending> incoming_, pending_;
+    int running_count_ = 0;
+    std::deque<fftc_completion> done_;
+    std::unordered_map<void*, std::pair<size_t, size_t>> live_;
+    std::map<std::tuple<int64_t, int, int>, fftc_plan_t> plans_;
+    std::vector<fftc_plan_t> retired_;
+    fftc_server_stats stats_{};
+};
+
+std::mutex g_server_mu;
+Server* g_server = nullptr;
+bool g_server_stopping = false;
+
+}  // namespace
+}  // namespace fftc
+
+using namespace fftc;
+
+extern "C" {
+
+int64_t fftc_now_ns(void) { return now_ns(); }
+
+fftc_status fftc_server_start(const fftc_server_config* cfg) {
+    clear_error();
+    if (!cfg) return fail(FFTC_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->executor != FFTC_EXECUTOR_GPU && cfg->executor != FFTC_EXECUTOR_MOCK)
+        return fail(FFTC_ERR_INVALID_ARG, "bad executor");
+    if (cfg->budget_bytes < 256) return fail(FFTC_ERR_INVALID_ARG, "budget too small");
+    std::lock_guard<std::mutex> g(g_server_mu);
+    if (g_server) return fail(FFTC_ERR_INVALID_ARG, "server already running");
+    try {
+        Server* s = new Server();
+        fftc_status st = s->start(*cfg);
+        if (st != FFTC_OK) {
+            std::string keep = fftc_last_error();
+            s->stop(false);
+            delete s;
+            return fail(st, keep);
+        }
+        g_server = s;
+        return FFTC_OK;
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_server_start");
+    }
+}
+
+fftc_status fftc_server_prepare(int64_t n, int direction, int dtype, int64_t max_batch) {
+    clear_error();
+    std::lock_guard<std::mutex> g(g_server_mu);
+    if (!g_server) return fail(FFTC_ERR_SHUTDOWN, "server not running");
+    return g_server->prepare(n, direction, dtype, max_batch);
+}
+
+fftc_status fftc_submit(const fftc_request* req) {
+    clear_error();
+    if (!req) return fail(FFTC_ERR_INVALID_ARG, "req is NULL");
+    std::lock_guard<std::mutex> g(g_server_mu);
+    if (!g_server) return fail(FFTC_ERR_SHUTDOWN, "server not running");
+    return g_server->submit(*req);
+}
+
+fftc_status fftc_poll(fftc_completion* out, int max, int* n_out) {
+    clear_error();
+    if (!n_out || (max > 0 && !out)) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(g_server_mu);
+    if (!g_server) return fail(FFTC_ERR_SHUTDOWN, "server not running");
+    *n_out = g_server->poll(out, max);
+    return FFTC_OK;
+}
+
+fftc_status fftc_release(void* out) {
+    clear_error();
+    std::lock_guard<std::mutex> g(g_server_mu);
+    if (!g_server) return fail(FFTC_ERR_SHUTDOWN, "server not running");
+    return g_server->release(out);
+}
+
+fftc_status fftc_server_stats_get(fftc_server_stats* s) {
+    clear_error();
+    if (!s) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(g_server_mu);
+    if (!g_server) return fail(FFTC_ERR_SHUTDOWN, "server not running");
+    g_server->stats(s);
+    return FFTC_OK;
+}
+
+fftc_status fftc_server_stop(int drain) {
+    clear_error();
+    Server* s;
+    {
+        std::lock_guard<std::mutex> g(g_server_mu);
+        s = g_server;
+        if (!s || g_server_stopping) return fail(FFTC_ERR_SHUTDOWN, "server not running");
+        g_server_stopping = true;
+    }
+    // the server stays reachable (poll, release) while it drains
+    fftc_status st = s->stop(drain != 0);
+    {
+        std::lock_guard<std::mutex> g(g_server_mu);
+        g_server = nullptr;
+        g_server_stopping = false;
+    }
+    delete s;
+    return st;
+}
+
+}  // extern "C"

@@ -15,6 +15,6 @@ inline bool is_split_dtype(int dtype) {
 bool split_supported(int64_t n);
 std::vector<int> split_radices(int64_t n);
 int split_threads(int64_t n);
-fftc_status launch_split(const fftc_plan_s* p, const void* in, void* out, hipStream_t s);
+fftc_status launch_split(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);
 
 }  // namespace fftc

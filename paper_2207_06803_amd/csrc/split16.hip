@@ -334,7 +334,7 @@ std::vector<int> split_radices(int64_t n) {
 
 int split_threads(int64_t n) { return 64 * (n <= 4096 ? (n / 256 < 4 ? (n / 256 < 1 ? 1 : (int)(n / 256)) : 4) : (int)(n / 1024)); }
 
-fftc_status launch_split(const fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
+fftc_status launch_split(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s) {
     const bool inv = p->direction == FFTC_INVERSE;
     const void* fn = nullptr;
     switch (p->dtype) {
@@ -348,7 +348,6 @@ fftc_status launch_split(const fftc_plan_s* p, const void* in, void* out, hipStr
     const float2* tin = static_cast<const float2*>(in);
     float2* tout = static_cast<float2*>(out);
     const float2* tw = static_cast<const float2*>(p->tw);
-    int64_t batch = p->batch;
     void* args[] = {(void*)&tin, (void*)&tout, (void*)&tw, (void*)&batch};
     hipError_t e = hipLaunchKernel(fn, dim3((unsigned)batch), dim3(split_threads(p->n)), args, 0, s);
     if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(split_fft)");
