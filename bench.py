@@ -1,15 +1,27 @@
-"""Benchmark: batched complex FFT throughput on one MI355X.
+"""Benchmark: batched complex FFTs on one MI355X.
 
-A step is one pass of the batched-FFT hot path over the headline workload:
+Headline step (the `value`): one pass of the batched Stockham path over
 complex64 transforms of N = 256, 1024 and 4096, each at batch 2^24 / N
 (2^24 elements, 256 MiB of algorithmic HBM traffic per launch), forward and
 inverse -- six launches per step.  Inputs are seeded uniform[-1, 1) and
 resident in HBM before timing; four input/output buffer pairs (1 GiB) rotate
-so the 256 MB last-level cache does not serve the reads.
+so the 256 MB last-level cache cannot serve the reads.
+
+The same JSON line carries the other workloads as extras (each timed with
+HIP events on the stream its kernels run on):
+  * 64-point complex64, 1024 transforms: time per launch
+  * complex128 at the headline sizes
+  * 10,000 mixed-length transforms: one persistent launch (hipGraph) vs the
+    per-length path (37 batched launches, graph-captured)
+  * split-precision MFMA modes at N = 1024, 4096, 16384, batch 8192: time and
+    error against the complex128 GPU path
+  * serving: 20,000 Poisson-arriving requests, p50/p99 latency
+and the FP64 oracle timed on the host cores as the CPU baseline.
 
 Prints one JSON line.  `value` is GFLOP/s in the 5 N log2 N convention.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -22,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0}
 SIZES = (256, 1024, 4096)
 ELEMS = 1 << 24
 NBUF = 4
@@ -36,42 +49,294 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--extras", default="c128",
-                    help="comma list of extra measurements: c128 (default), none")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time only the headline step (used for profiling runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run plain 128 MiB device copies (counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-rate", type=float, default=10000.0)
     return ap.parse_args()
 
 
-class KernelTimer:
-    """Average duration of repeated launches of one plan, timed with HIP events
-    recorded on the stream the kernels run on."""
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP-event timing on torch's current stream (the stream fftc launches on)."""
 
     def __init__(self, torch):
         self.torch = torch
+        self.s = torch.cuda.current_stream()
 
-    def time(self, plan, xs, ys, reps):
+    def avg_ms(self, fn, reps, warm=3):
         torch = self.torch
-        s = torch.cuda.current_stream()
+        for i in range(warm):
+            fn(i)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        for i in range(3):
-            plan.execute(xs[i % len(xs)], ys[i % len(ys)], s)
-        e0.record(s)
+        e0.record(self.s)
         for i in range(reps):
-            plan.execute(xs[i % len(xs)], ys[i % len(ys)], s)
-        e1.record(s)
+            fn(i)
+        e1.record(self.s)
         e1.synchronize()
-        return e0.elapsed_time(e1) / reps  # ms
+        return e0.elapsed_time(e1) / reps
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2207_06803_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".inc", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_key)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
+def headline(args, torch, fftc, synth, timer):
+    dev = torch.device("cuda:0")
+    host = synth.uniform_complex(synth.rng(1, 0), (ELEMS,), np.complex64)
+    xs = [torch.from_numpy(host).to(dev) for _ in range(NBUF)]
+    for i in range(1, NBUF):
+        xs[i].mul_(1.0 + 0.0625 * i)
+    ys = [torch.empty_like(xs[0]) for _ in range(NBUF)]
+    plans = [fftc.Plan(n, ELEMS // n, d, "c64") for n in SIZES for d in (fftc.FORWARD, fftc.INVERSE)]
+    step_flops = sum(flops(p.n, p.batch) for p in plans)
+    step_bytes = sum(16.0 * p.n * p.batch for p in plans)
+    s = timer.s
+
+    def step(i):
+        for j, p in enumerate(plans):
+            k = (i * len(plans) + j) % NBUF
+            p.execute(xs[k], ys[k], s)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for i in range(args.steps):
+        step(i)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    per = {}
+    for p in plans:
+        avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % NBUF], ys[i % NBUF], s), 20)
+        d = p.describe()
+        per[f"c64_{p.n}_{'fwd' if p.direction < 0 else 'inv'}"] = {
+            "us": avg * 1e3, "gflops": flops(p.n, p.batch) / (avg * 1e-3) / 1e9,
+            "hbm_gbs": 16.0 * p.n * p.batch / (avg * 1e-3) / 1e9,
+            "radices": d["radices"], "variant": d["variant"]}
+    for p in plans:
+        p.close()
+    res = {"ms_per_step": ms_step, "value": step_flops / (ms_step * 1e-3) / 1e9,
+           "hbm_gbs": step_bytes / (ms_step * 1e-3) / 1e9, "wall_s": wall, "per_kernel": per}
+    del xs, ys
+    torch.cuda.empty_cache()
+    return res
+
+
+def config1(torch, fftc, synth, timer):
+    x = torch.from_numpy(synth.uniform_complex(synth.rng(0), (1024 * 64,), np.complex64)).to("cuda")
+    y = torch.empty_like(x)
+    with fftc.Plan(64, 1024, fftc.FORWARD, "c64") as p:
+        avg = timer.avg_ms(lambda i: p.execute(x, y, timer.s), 200)
+        d = p.describe()
+    return {"workload": "forward complex64, N=64, 1024 transforms", "us_per_launch": avg * 1e3,
+            "gflops": flops(64, 1024) / (avg * 1e-3) / 1e9, "radices": d["radices"]}
+
+
+def c128(torch, fftc, synth, timer):
+    xs = [torch.from_numpy(synth.uniform_complex(synth.rng(1, 1), (ELEMS,), np.complex128)).to("cuda")
+          for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    out = {}
+    for n in SIZES:
+        for d in (fftc.FORWARD, fftc.INVERSE):
+            with fftc.Plan(n, ELEMS // n, d, "c128") as p:
+                avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % 2], ys[i % 2], timer.s), 10)
+            out[f"c128_{n}_{'fwd' if d < 0 else 'inv'}"] = {
+                "us": avg * 1e3, "gflops": flops(n, ELEMS // n) / (avg * 1e-3) / 1e9,
+                "hbm_gbs": 32.0 * ELEMS / (avg * 1e-3) / 1e9}
+    del xs, ys
+    torch.cuda.empty_cache()
+    return out
+
+
+def config3(torch, fftc, synth, timer):
+    g = synth.rng(2)
+    lengths = synth.draw_mixed_sizes(g, 10000)
+    tot = int(lengths.sum())
+    fl = float(sum(flops(int(n), 1) for n in lengths))
+    x = torch.from_numpy(synth.uniform_complex(g, (tot,), np.complex64)).to("cuda")
+    y = torch.empty_like(x)
+    t0 = time.perf_counter()
+    tuned = {}
+    for n in synth.mixed_size_set():
+        rs, us = fftc.autotune(n, max(1, (1 << 21) // n), "c64", reps=5)
+        tuned[n] = rs
+    tune_s = time.perf_counter() - t0
+    with fftc.plan_mixed(lengths, fftc.FORWARD, "c64") as p:
+        d = p.describe()
+        mixed_ms = timer.avg_ms(lambda i: p.execute(x, y, timer.s), 50)
+    # per-length path: the same transforms grouped by length, 37 batched plans
+    uniq, counts = np.unique(lengths, return_counts=True)
+    plans = [fftc.Plan(int(n), int(c), fftc.FORWARD, "c64") for n, c in zip(uniq, counts)]
+    offs = np.concatenate([[0], np.cumsum(uniq * counts)])
+    xg, yg = torch.empty_like(x), torch.empty_like(x)
+
+    def per_size(_=0):
+        for i, q in enumerate(plans):
+            q.execute(xg[int(offs[i]):], yg[int(offs[i]):], torch.cuda.current_stream())
+
+    eager_ms = timer.avg_ms(per_size, 20)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        per_size()
+    graph_ms = timer.avg_ms(lambda i: graph.replay(), 50)
+    for q in plans:
+        q.close()
+    return {"workload": "10,000 complex64 transforms, 37 lengths 8..4096 (2^k, 3*2^k, 5*2^k, 7*2^k), "
+                        "one persistent launch in a hipGraph",
+            "elements": tot, "bytes": 16 * tot, "gflop": fl / 1e9,
+            "persistent_us": mixed_ms * 1e3, "persistent_gflops": fl / (mixed_ms * 1e-3) / 1e9,
+            "persistent_hbm_gbs": 16 * tot / (mixed_ms * 1e-3) / 1e9,
+            "per_length_graph_us": graph_ms * 1e3, "per_length_eager_us": eager_ms * 1e3,
+            "speedup_vs_per_length_graph": graph_ms / mixed_ms,
+            "work_items": d["mixed_items"], "persistent_groups": d["persistent_groups"],
+            "autotune_s": tune_s, "tuned_lists": {str(k): v for k, v in tuned.items()}}
+
+
+def config4(torch, fftc, synth, timer):
+    out = {}
+    modes = ("c64", "split_f16", "split_bf16", "split3_bf16", "f16")
+    mfma_per_group = {"split_f16": 6, "split_bf16": 6, "split3_bf16": 12, "f16": 2}
+    for n in (1024, 4096, 16384):
+        b = 8192
+        xh = synth.gaussian_complex(synth.rng(4, n), (b * n,), np.complex64)
+        x = torch.from_numpy(xh).to("cuda")
+        del xh
+        y = torch.empty_like(x)
+        # reference: the complex128 GPU path on the same (upcast) input
+        x128 = x.to(torch.complex128)
+        ref = torch.empty_like(x128)
+        with fftc.Plan(n, b, fftc.FORWARD, "c128") as p:
+            p.execute(x128, ref, timer.s)
+            ms128 = timer.avg_ms(lambda i: p.execute(x128, ref, timer.s), 3)
+        torch.cuda.synchronize()
+        del x128
+        refn = ref.view(b, n)
+        refnorm = torch.linalg.vector_norm(refn, dim=1)
+        row = {"c128_us": ms128 * 1e3}
+        for mode in modes:
+            with fftc.Plan(n, b, fftc.FORWARD, mode) as p:
+                ms = timer.avg_ms(lambda i: p.execute(x, y, timer.s), 5)
+                torch.cuda.synchronize()
+                err = (torch.linalg.vector_norm(y.view(b, n).to(torch.complex128) - refn, dim=1) / refnorm)
+                e = {"us": ms * 1e3, "gflops": flops(n, b) / (ms * 1e-3) / 1e9,
+                     "hbm_gbs": 16.0 * n * b / (ms * 1e-3) / 1e9,
+                     "rel_l2_max": float(err.max()), "rel_l2_mean": float(err.mean())}
+                if mode in mfma_per_group:
+                    s16 = 0
+                    m = n
+                    while m % 16 == 0:
+                        m //= 16
+                        s16 += 1
+                    groups = s16 * (n // 256)
+                    mf = groups * mfma_per_group[mode] * 2 * 16 * 16 * 32 * b
+                    e["mfma_tflops"] = mf / (ms * 1e-3) / 1e12
+                    e["mfma_util"] = e["mfma_tflops"] / MFMA_PEAK_TFLOPS["f16"]
+                row[mode] = e
+        out[str(n)] = row
+        del x, y, ref, refn
+        torch.cuda.empty_cache()
+    return {"workload": "forward complex64, batch 8192, Gaussian(0,1) inputs; error = relative L2 "
+                        "per transform against the complex128 GPU path", "by_n": out}
+
+
+def config5(args, torch, fftc, synth):
+    from paper_2207_06803_amd import server as srv
+    g = synth.rng(5)
+    reqs = synth.serving_requests(synth.rng(5, 99), args.serve_requests, args.serve_rate)
+    pool_elems = (1 << 24) + (1 << 20)
+    pool = torch.from_numpy(synth.uniform_complex(g, (pool_elems,), np.complex64)).to("cuda")
+    offs = g.integers(0, (1 << 20), size=args.serve_requests)
+    budget = 64 << 30
+    srv.start(budget, n_streams=4, max_inflight=64)
+    try:
+        for n in sorted(set(int(v) for v in reqs["n"])):
+            for d in (fftc.FORWARD, fftc.INVERSE):
+                srv.prepare(n, d, "c64", 256)
+        torch.cuda.synchronize()
+        N = args.serve_requests
+        base = pool.data_ptr()
+        t0 = srv.now_ns() + 2_000_000
+        sched = t0 + (reqs["arrival_s"] * 1e9).astype(np.int64)
+        done = {}
+        i = 0
+        last = srv.now_ns()
+        while len(done) < N:
+            now = srv.now_ns()
+            if now - last > 60_000_000_000:
+                raise RuntimeError(f"serving made no progress for 60 s ({len(done)} of {N} done)")
+            while i < N and sched[i] <= now:
+                rc = srv.submit(int(reqs["n"][i]), int(reqs["batch"][i]), int(reqs["direction"][i]),
+                                base + 8 * int(offs[i]), i, int(sched[i]))
+                if rc != 0:
+                    raise RuntimeError(f"submit failed with status {rc}")
+                i += 1
+            for c in srv.poll():
+                if c["status"] != 0:
+                    raise RuntimeError(f"request {c['tag']} failed: {c['status']}")
+                done[c["tag"]] = c
+                srv.release(c["out"])
+                last = now
+        st = srv.stats()
+    finally:
+        srv.stop(drain=False)
+    lat = np.array([(done[k]["done_ns"] - done[k]["arrival_ns"]) * 1e-3 for k in range(N)])
+    q = np.array([(done[k]["admit_ns"] - done[k]["arrival_ns"]) * 1e-3 for k in range(N)])
+    fl = float(sum(flops(int(n), int(b)) for n, b in zip(reqs["n"], reqs["batch"])))
+    by = float(sum(16.0 * int(n) * int(b) for n, b in zip(reqs["n"], reqs["batch"])))
+    span = (max(c["done_ns"] for c in done.values()) - min(int(s) for s in sched)) * 1e-9
+    return {"workload": f"{N} complex64 requests, Poisson arrivals at {args.serve_rate:.0f}/s, "
+                        "batch U[1,256], N in 2^6..2^16, half forward / half inverse, budget 64 GiB",
+            "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+            "mean_us": float(lat.mean()), "max_us": float(lat.max()),
+            "queue_p99_us": float(np.percentile(q, 99)),
+            "sustained_gflops": fl / span / 1e9, "sustained_hbm_gbs": by / span / 1e9,
+            "span_s": span, "offered_gbs": by / (reqs["arrival_s"][-1] + 1e-9) / 1e9,
+            "peak_budget_bytes": st["peak_bytes"], "max_inflight_seen": st["max_inflight_seen"]}
 
 
 def cpu_baseline(seconds):
     """The FP64 O(N^2) oracle on the host cores, on a bounded sample of the
-    same workload (transforms of each N, both directions)."""
+    headline workload (transforms of each N, both directions)."""
     import oracle
     from paper_2207_06803_amd import synth
     threads = oracle.max_threads()
     g = synth.rng(1, 77)
-    # calibrate: one transform per size
     per = {}
     for n in SIZES:
         x = synth.uniform_complex(g, (threads, n), np.complex64)
@@ -91,117 +356,76 @@ def cpu_baseline(seconds):
             tot_flops += flops(n, cnt)
     return {"value": tot_flops / tot_t / 1e9, "unit": "GFLOP/s (5 N log2 N)", "cores": threads,
             "kind": "oracle",
-            "sample": "FP64 O(N^2) oracle, complex64 inputs, forward+inverse, transforms per N: "
-                      + ", ".join(f"{n}:{c}" for n, c in counts.items()),
-            "seconds": tot_t}
+            "sample": "FP64 O(N^2) oracle on complex64 inputs, forward+inverse, transforms per N: "
+                      + ", ".join(f"{n}:{c}" for n, c in counts.items()) + f" ({tot_t:.1f} s)"}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}), flush=True)
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
+                                   "this build (--gpus must be 1)", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import torch
     from paper_2207_06803_amd import fftc, synth
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    # seeded inputs, generated once on the host and copied to HBM
-    g = synth.rng(1, 0)
-    host = synth.uniform_complex(g, (ELEMS,), np.complex64)
-    xs = [torch.from_numpy(host).to(dev) for _ in range(NBUF)]
-    for i in range(1, NBUF):
-        xs[i].mul_(1.0 + 0.0625 * i)
-    ys = [torch.empty_like(xs[0]) for _ in range(NBUF)]
-
-    plans = []
-    for n in SIZES:
-        for d in (fftc.FORWARD, fftc.INVERSE):
-            plans.append(fftc.Plan(n, ELEMS // n, d, "c64"))
-    step_flops = sum(flops(p.n, p.batch) for p in plans)
-    step_bytes = sum(16.0 * p.n * p.batch for p in plans)
-    s = torch.cuda.current_stream()
-
-    def step(i):
-        for j, p in enumerate(plans):
-            k = (i * len(plans) + j) % NBUF
-            p.execute(xs[k], ys[k], s)
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_wall0 = time.perf_counter()
-    e0.record(s)
-    for i in range(args.steps):
-        step(i)
-    e1.record(s)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall0
-    ms = e0.elapsed_time(e1)
-    ms_step = ms / args.steps
-    value = step_flops / (ms_step * 1e-3) / 1e9
-
-    # per-kernel average durations (HIP events on the launch stream)
-    kt = KernelTimer(torch)
-    per = {}
-    for p in plans:
-        avg = kt.time(p, xs, ys, 20)
-        per[f"{p.n}_{'fwd' if p.direction < 0 else 'inv'}"] = {
-            "ms": avg, "gflops": flops(p.n, p.batch) / (avg * 1e-3) / 1e9,
-            "hbm_gbs": 16.0 * p.n * p.batch / (avg * 1e-3) / 1e9,
-            "radices": p.describe()["radices"], "variant": p.describe()["variant"]}
-    dom_key = max(per, key=lambda k: per[k]["ms"])
-    dom = per[dom_key]
-    roofline = {"bound": "hbm", "kernel": f"stockham c64 N={dom_key}", "achieved": dom["hbm_gbs"],
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbs"] / HBM_PEAK_GBS,
-                "traffic": None}
-
+    torch.cuda.set_device(0)
+    timer = Timer(torch)
+    if args.calibrate_copy:
+        # a plain copy of known size: 2^24 complex64 = 128 MiB read + 128 MiB written
+        x = torch.from_numpy(synth.uniform_complex(synth.rng(1, 0), (ELEMS,), np.complex64)).to("cuda")
+        y = torch.empty_like(x)
+        avg = timer.avg_ms(lambda i: y.copy_(x), 10)
+        print(json.dumps({"copy_bytes_read": 8 * ELEMS, "copy_bytes_written": 8 * ELEMS,
+                          "us": avg * 1e3, "gbs": 16.0 * ELEMS / (avg * 1e-3) / 1e9}), flush=True)
+        return
+    log("headline step ...")
+    h = headline(args, torch, fftc, synth, timer)
+    dom_key = max(h["per_kernel"], key=lambda k: h["per_kernel"][k]["us"])
+    dom = h["per_kernel"][dom_key]
+    n_dom = int(dom_key.split("_")[1])
+    alg_bytes = 16.0 * ELEMS
+    roofline = {"bound": "hbm", "kernel": f"stockham {dom_key} ({dom['variant']}, radices {dom['radices']})",
+                "achieved": alg_bytes / (dom["us"] * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": alg_bytes / (dom["us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                "traffic": measured_traffic(dom_key), "algorithmic_bytes_per_launch": alg_bytes,
+                "n": n_dom}
     extras = {}
-    if "c128" in args.extras:
-        xs128 = [torch.from_numpy(synth.uniform_complex(synth.rng(1, 1), (ELEMS,), np.complex128)).to(dev)
-                 for _ in range(2)]
-        ys128 = [torch.empty_like(xs128[0]) for _ in range(2)]
-        for n in SIZES:
-            for d in (fftc.FORWARD, fftc.INVERSE):
-                with fftc.Plan(n, ELEMS // n, d, "c128") as p:
-                    avg = kt.time(p, xs128, ys128, 10)
-                extras[f"c128_{n}_{'fwd' if d < 0 else 'inv'}"] = {
-                    "ms": avg, "gflops": flops(n, ELEMS // n) / (avg * 1e-3) / 1e9,
-                    "hbm_gbs": 32.0 * ELEMS / (avg * 1e-3) / 1e9}
-        del xs128, ys128
-
+    if not args.only_headline:
+        for name, fn in (("config1_n64", lambda: config1(torch, fftc, synth, timer)),
+                         ("c128", lambda: c128(torch, fftc, synth, timer)),
+                         ("config3_mixed", lambda: config3(torch, fftc, synth, timer)),
+                         ("config4_split_precision", lambda: config4(torch, fftc, synth, timer)),
+                         ("config5_serving", lambda: config5(args, torch, fftc, synth))):
+            log(f"{name} ...")
+            extras[name] = fn()
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.only_headline:
+        log("cpu baseline ...")
         cpu = cpu_baseline(args.cpu_seconds)
-
     out = {
         "metric": "complex64 FFT GFLOP/s (5Nlog2N) & HBM GB/s; served p50/p99 latency",
-        "value": value,
+        "value": h["value"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64 (fp32 arithmetic)",
         "data": "synthetic: seeded uniform[-1,1) re/im",
-        "config": {"workload": "batched complex64 FFT, N in {256,1024,4096}, batch 2^24/N, "
+        "config": {"workload": "batched complex64 FFT, N in {256,1024,4096}, batch 2^24/N each, "
                                "forward+inverse (6 launches per step)",
                    "elements_per_launch": ELEMS, "rotating_buffers": NBUF},
-        "hbm_gbs": step_bytes / (ms_step * 1e-3) / 1e9,
-        "wall_s": wall,
-        "per_kernel": per,
+        "hbm_gbs": h["hbm_gbs"],
+        "per_kernel": h["per_kernel"],
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extras": extras,
     }
     print(json.dumps(out), flush=True)
-    for p in plans:
-        p.close()
 
 
 if __name__ == "__main__":
