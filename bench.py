@@ -55,6 +55,8 @@ def parse():
                     help="time only the headline step (used for profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 128 MiB device copies (counter calibration)")
+    ap.add_argument("--rocpd-summary", nargs="+", metavar="DB",
+                    help="print per-kernel durations and counters from rocprofv3 databases, then exit")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=10000.0)
     return ap.parse_args()
@@ -360,8 +362,38 @@ def cpu_baseline(seconds):
                       + ", ".join(f"{n}:{c}" for n, c in counts.items()) + f" ({tot_t:.1f} s)"}
 
 
+def rocpd_summary(paths):
+    """Per-kernel call count / mean duration (kernel traces) or mean counter
+    value per dispatch (counter runs) from rocprofv3's SQLite output."""
+    import re
+    import sqlite3
+    for path in paths:
+        db = sqlite3.connect(path)
+        cur = db.cursor()
+        print(f"# {os.path.basename(path)}")
+        # top_kernels reports durations in microseconds
+        rows = cur.execute("select name, total_calls, average, percentage from top_kernels").fetchall()
+        if rows:
+            print("| kernel | calls | mean duration (us) | share of GPU time |")
+            print("|---|---|---|---|")
+            for name, calls, avg, pct in rows:
+                print(f"| `{re.sub(r'[(].*', '', name)}` | {calls} | {avg:.2f} | {pct:.1f}% |")
+        agg = {}
+        for name, cn, val in cur.execute("select kernel_name, counter_name, value from counters_collection"):
+            agg.setdefault((re.sub(r'[(].*', '', name), cn), []).append(val)
+        if agg:
+            print("| kernel | counter | dispatches | mean per dispatch |")
+            print("|---|---|---|---|")
+            for (name, cn), vals in sorted(agg.items()):
+                print(f"| `{name}` | {cn} | {len(vals)} | {sum(vals) / len(vals):.1f} |")
+        print()
+
+
 def main():
     args = parse()
+    if args.rocpd_summary:
+        rocpd_summary(args.rocpd_summary)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
                                    "this build (--gpus must be 1)", "n_gpus": args.gpus}), flush=True)
