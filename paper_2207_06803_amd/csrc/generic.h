@@ -46,12 +46,7 @@ __device__ __forceinline__ void gen_stage(const C* gin, C* gout, C* lds, const C
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[i][r] = lds[lds_pad(j + r * nr)];
             }
-            if (ns > 1) {
-                const int k = j - div_ns(j, s) * ns;
-                const C* twq = tw + s.twoff + k;
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twq[(r - 1) * ns]);
-            }
+            if (ns > 1) apply_twiddles_ns<R>(v[i], tw + s.twoff + (j - div_ns(j, s) * ns), ns);
             Codelet<R, C>::run(v[i]);
         }
     }

@@ -38,6 +38,40 @@ template <bool INV, typename C> __device__ __forceinline__ void st_out(C* p, C v
     __builtin_nontemporal_store(t, reinterpret_cast<V*>(p));
 }
 
+// Multiply v[r] (r >= 1) by w_{Ns R}^{r k}, with tq = table + k (entry
+// [(r-1) Ns + k] at tq[(r-1) ns]).  For R = 8 and 16 only the factors
+// r = 1, 2, 3 and r = 4, 8, 12 are read and the rest formed as one product
+// w^{r k} = w^{(r mod 4) k} w^{4 (r div 4) k}: 6 loads instead of 15 for
+// radix 16 (one extra rounding in the formed factors).
+template <int R, typename C>
+__device__ __forceinline__ void apply_twiddles_ns(C* v, const C* __restrict__ tq, int ns) {
+    if constexpr (R == 16 || R == 8) {
+        C a[4], b[4];
+        a[1] = tq[0 * ns];
+        a[2] = tq[1 * ns];
+        a[3] = tq[2 * ns];
+        b[1] = tq[3 * ns];
+        if constexpr (R == 16) {
+            b[2] = tq[7 * ns];
+            b[3] = tq[11 * ns];
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const int ra = r & 3, rb = r >> 2;
+            const C w = (rb == 0) ? a[ra] : (ra == 0 ? b[rb] : cmul(a[ra], b[rb]));
+            v[r] = cmul(v[r], w);
+        }
+    } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tq[(r - 1) * ns]);
+    }
+}
+
+template <int R, int NS, typename C>
+__device__ __forceinline__ void apply_twiddles(C* v, const C* __restrict__ tq) {
+    apply_twiddles_ns<R>(v, tq, NS);
+}
+
 // ---------------------------------------------------------------------------
 // Compile-time specialised kernel: N, radix sequence, threads per transform
 // (TPT) and transforms per workgroup (T) are template parameters, so every
@@ -82,11 +116,7 @@ __device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K:
                     v[i][r] = lds[lds_pad(j + r * NR)];
                 }
             }
-            if constexpr (NS > 1) {
-                const int k = j % NS;
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[TWOFF + (r - 1) * NS + k]);
-            }
+            if constexpr (NS > 1) apply_twiddles<R, NS>(v[i], tw + TWOFF + j % NS);
             Codelet<R, C>::run(v[i]);
         }
     }
