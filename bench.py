@@ -186,6 +186,26 @@ def c128(torch, fftc, synth, timer):
     return out
 
 
+def two_pass(torch, fftc, synth, timer):
+    """Lengths beyond one workgroup's LDS (Eq. 2 four-step, two kernels)."""
+    xs = [torch.from_numpy(synth.uniform_complex(synth.rng(1, 2), (ELEMS,), np.complex64)).to("cuda")
+          for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    out = {}
+    for n in (32768, 65536, 1 << 20):
+        with fftc.Plan(n, ELEMS // n, fftc.FORWARD, "c64") as p:
+            d = p.describe()
+            avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % 2], ys[i % 2], timer.s), 10)
+        out[f"c64_{n}_fwd"] = {"us": avg * 1e3, "gflops": flops(n, ELEMS // n) / (avg * 1e-3) / 1e9,
+                               "hbm_gbs_algorithmic": 16.0 * ELEMS / (avg * 1e-3) / 1e9,
+                               "hbm_gbs_moved": 32.0 * ELEMS / (avg * 1e-3) / 1e9,
+                               "split": [d["split_m"], d["split_k"]]}
+    del xs, ys
+    torch.cuda.empty_cache()
+    return {"workload": "complex64 forward, 2^24 elements per launch; each pass reads and writes "
+                        "every element (twice the algorithmic bytes)", "by_n": out}
+
+
 def config3(torch, fftc, synth, timer):
     g = synth.rng(2)
     lengths = synth.draw_mixed_sizes(g, 10000)
@@ -426,6 +446,7 @@ def main():
     if not args.only_headline:
         for name, fn in (("config1_n64", lambda: config1(torch, fftc, synth, timer)),
                          ("c128", lambda: c128(torch, fftc, synth, timer)),
+                         ("two_pass", lambda: two_pass(torch, fftc, synth, timer)),
                          ("config3_mixed", lambda: config3(torch, fftc, synth, timer)),
                          ("config4_split_precision", lambda: config4(torch, fftc, synth, timer)),
                          ("config5_serving", lambda: config5(args, torch, fftc, synth))):

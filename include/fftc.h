@@ -164,10 +164,11 @@ int64_t fftc_max_single_n(int dtype);
  * factors <= 7.  The uneven batch runs as one persistent launch: equal lengths
  * form classes with their own radix list (tuning database or heuristic), work
  * items are ordered longest first and pulled by the resident workgroups from
- * an atomic counter.  The counter reset and the launch are recorded in a
- * hipGraph at plan time; fftc_execute replays it on the caller's stream
- * (updating the graph's pointer arguments when in/out change).  Executions of
- * one mixed plan must not overlap (they share the work counter).
+ * an atomic counter, which the last workgroup to finish clears again.  The
+ * launch is recorded in a hipGraph at plan time; fftc_execute replays it on
+ * the caller's stream (updating the graph's pointer arguments when in/out
+ * change).  Executions of one mixed plan must not overlap (they share the
+ * work counter).
  */
 fftc_status fftc_plan_mixed(const int64_t *n, int64_t count, int direction, int dtype,
                             fftc_plan_t *plan_out);

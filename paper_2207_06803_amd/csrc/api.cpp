@@ -158,8 +158,19 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
             p->variant = FFTC_VARIANT_TWO_PASS;
             p->m = m;
             p->k = k;
-            p->r1 = choose_radices(m, dtype);
-            p->r2 = choose_radices(k, dtype);
+            // prefer a column list with compiled kernels: the tuned or
+            // preferred list, else the planner's first candidate
+            auto pick = [&](int64_t len, const FourStepEntry** fs) {
+                std::vector<int> rs = choose_radices(len, dtype);
+                *fs = find_fourstep(dtype, len, rs);
+                if (!*fs) {
+                    auto c = radix_candidates(len, 1);
+                    if (!c.empty() && (*fs = find_fourstep(dtype, len, c[0])) != nullptr) rs = c[0];
+                }
+                return rs;
+            };
+            p->r1 = pick(m, &p->fs1);
+            p->r2 = pick(k, &p->fs2);
             const int tc = two_pass_cols(dtype);
             int tpt1, tpt2, tdummy;
             launch_shape(m, p->r1, (int)cs, &tpt1, &tdummy);
@@ -174,14 +185,17 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
                 p->tw2_off = e1;
                 const int64_t e2 = stage_segments(p->r2, e1, &segs);
                 p->twn_off = e1 + e2;
-                segs.push_back({p->twn_off, n, n, n});
+                // w_N^e for e < N as fine (e mod 1024) x coarse (e div 1024) tables
+                const int64_t nhi = (n + kTwSplit - 1) / kTwSplit;
+                segs.push_back({p->twn_off, kTwSplit, kTwSplit, n, 1});
+                segs.push_back({p->twn_off + kTwSplit, nhi, nhi, n, kTwSplit});
                 fill_gen_desc(m, p->r1, tpt1, tc, p->tw1_off, &p->pass1);
                 fill_gen_desc(k, p->r2, tpt2, tc, p->tw2_off, &p->pass2);
                 p->radices = p->r1;
                 p->radices.insert(p->radices.end(), p->r2.begin(), p->r2.end());
                 p->tpt = tpt1;
                 p->t = tc;
-                st = alloc_tables(p, segs, p->twn_off + n);
+                st = alloc_tables(p, segs, p->twn_off + kTwSplit + nhi);
             }
             if (st == FFTC_OK && !t_plan_no_scratch) {
                 p->scratch_bytes = (size_t)batch * (size_t)n * cs;

@@ -80,7 +80,9 @@ four_step_pass(const cplx<Real>* src, cplx<Real>* dst, const cplx<Real>* __restr
             const int p = l - c * len;
             if (c < cols) {
                 const int i = col0 + c;
-                dst[base + (int64_t)i * len + p] = cmul(lds[c * ldl + lds_pad(p)], twn[(int64_t)i * p]);
+                const int e = i * p;  // < N <= 2^20
+                const C w = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
+                dst[base + (int64_t)i * len + p] = cmul(lds[c * ldl + lds_pad(p)], w);
             }
         }
     } else {
@@ -192,7 +194,16 @@ static fftc_status launch_two_pass_chunk(const fftc_plan_s* p, const cplx<Real>*
                                          cplx<Real>* tout, const cplx<Real>* tw, const cplx<Real>* twn,
                                          int tc, size_t csz, int64_t nb, hipStream_t s) {
     using C = cplx<Real>;
-    {
+    if (p->fs1) {  // compiled column kernels
+        const FourStepEntry* f = p->fs1;
+        const C* tw1 = tw + p->tw1_off;
+        int64_t n = p->n;
+        int ncols = (int)p->k;
+        void* args[] = {(void*)&tin, (void*)&mid, (void*)&tw1, (void*)&twn, (void*)&n, (void*)&ncols};
+        hipError_t e = hipLaunchKernel(f->fn[0][INV ? 1 : 0], dim3((unsigned)((p->k + f->tc - 1) / f->tc), (unsigned)nb),
+                                       dim3(f->tpt * f->tc), args, 0, s);
+        if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(fourstep pass 1)");
+    } else {
         const GenDesc& d = p->pass1;
         dim3 grid((unsigned)((p->k + tc - 1) / tc), (unsigned)nb);
         const size_t lds = (size_t)tc * lds_len(d.n) * csz;
@@ -201,7 +212,17 @@ static fftc_status launch_two_pass_chunk(const fftc_plan_s* p, const cplx<Real>*
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail_hip(e, "launch(four_step_pass 1)");
     }
-    {
+    if (p->fs2) {
+        const FourStepEntry* f = p->fs2;
+        const C* tw2 = tw + p->tw2_off;
+        const C* cmid = mid;
+        int64_t n = p->n;
+        int ncols = (int)p->m;
+        void* args[] = {(void*)&cmid, (void*)&tout, (void*)&tw2, (void*)&twn, (void*)&n, (void*)&ncols};
+        hipError_t e = hipLaunchKernel(f->fn[1][INV ? 1 : 0], dim3((unsigned)((p->m + f->tc - 1) / f->tc), (unsigned)nb),
+                                       dim3(f->tpt * f->tc), args, 0, s);
+        if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(fourstep pass 2)");
+    } else {
         const GenDesc& d = p->pass2;
         dim3 grid((unsigned)((p->m + tc - 1) / tc), (unsigned)nb);
         const size_t lds = (size_t)tc * lds_len(d.n) * csz;

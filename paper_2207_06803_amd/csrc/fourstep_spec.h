@@ -1,0 +1,95 @@
+// Two-pass (Eq. 2) plans with compiled Stockham bodies for the column
+// transforms.  Same data movement as four_step_pass in exec.hip -- a
+// workgroup owns TC adjacent columns, loads them with consecutive lanes on
+// consecutive columns (TC * sizeof(complex) contiguous bytes per row), runs
+// the column transforms LDS to LDS, and stores -- but the stages are a
+// compiled radix list, so every index is a compile-time shift or multiply.
+//   pass 1: column i < K of x (stride K), DFT_M, times w_N^{i p}, to row i
+//   pass 2: column p < M of z (stride M), DFT_K, to y (stride M)
+#pragma once
+#include "spec_table.h"
+
+namespace fftc {
+
+template <class K, int PASS, bool INV, int... Rs>
+__global__ void __launch_bounds__(K::TPT * K::T)
+fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C* __restrict__ tw,
+              const typename K::C* __restrict__ twn, int64_t n, int ncols) {
+    using C = typename K::C;
+    constexpr int LEN = K::N, TPT = K::TPT, TC = K::T, NTH = TPT * TC;
+    constexpr int LDSN = lds_len(LEN);
+    constexpr int TOT = TC * LEN, IT = (TOT + NTH - 1) / NTH;
+    __shared__ C lds[TC * LDSN];
+    const int tid = (int)threadIdx.x;
+    const int col0 = (int)blockIdx.x * TC;
+    const int cols = min(TC, ncols - col0);
+    const int64_t base = (int64_t)blockIdx.y * n;
+    // column-fastest load; a missing column reads column 0 of the tile
+    C buf[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int l = tid + i * NTH;
+        const int c = l % TC, j = min(l / TC, LEN - 1);
+        const int cc = c < cols ? c : 0;
+        C v = src[base + (int64_t)j * ncols + col0 + cc];
+        if (PASS == 1 && INV) v = cconj(v);
+        buf[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int l = tid + i * NTH;
+        if (l < TOT) lds[(l % TC) * LDSN + lds_pad(l / TC)] = buf[i];
+    }
+    __syncthreads();
+    const int tr = tid / TPT, t = tid - tr * TPT;
+    spec_stages<K, 1, 0, true, false, false, Rs...>(nullptr, nullptr, lds + tr * LDSN, tw, t, true, true);
+    if constexpr (PASS == 1) {
+        // row-major store of column i = col0 + c: z[i M + p] w_N^{i p} (i p < N),
+        // the factor formed from the fine and coarse tables
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int l = tid + i * NTH;
+            const int c = l / LEN, p = l % LEN;
+            if (l < TOT && c < cols) {
+                const int col = col0 + c;
+                const int e = col * p;  // < N <= 2^20
+                const C w = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
+                dst[base + (int64_t)col * LEN + p] = cmul(lds[c * LDSN + lds_pad(p)], w);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int l = tid + i * NTH;
+            const int c = l % TC, q = l / TC;
+            if (l < TOT && c < cols) {
+                C v = lds[c * LDSN + lds_pad(q)];
+                dst[base + (int64_t)q * ncols + col0 + c] = INV ? cconj(v) : v;
+            }
+        }
+    }
+}
+
+template <typename Real, int TC_, int N, int... Rs>
+struct FourStepInst {
+#ifdef FFTC_EXP_TC32
+    static constexpr int TC = N <= 512 ? 2 * TC_ : TC_;
+#else
+    static constexpr int TC = TC_;
+#endif
+    static constexpr int rs[sizeof...(Rs)] = {Rs...};
+    static constexpr int TPT = round_tpt(required_tpt(N, rs, (int)sizeof...(Rs)));
+    static_assert(TPT * TC <= 1024, "four-step tile too large");
+    static_assert(TC * lds_len(N) * (int)sizeof(cplx<Real>) <= kLdsMaxPerGroup, "four-step LDS too large");
+    using K = SpecCfg<Real, N, TPT, TC, false>;
+    static FourStepEntry entry(int dtype) {
+        FourStepEntry e{dtype, N, (int)sizeof...(Rs), {Rs...}, TPT, TC, {}};
+        e.fn[0][0] = reinterpret_cast<const void*>(&fourstep_spec<K, 1, false, Rs...>);
+        e.fn[0][1] = reinterpret_cast<const void*>(&fourstep_spec<K, 1, true, Rs...>);
+        e.fn[1][0] = reinterpret_cast<const void*>(&fourstep_spec<K, 2, false, Rs...>);
+        e.fn[1][1] = reinterpret_cast<const void*>(&fourstep_spec<K, 2, true, Rs...>);
+        return e;
+    }
+};
+
+}  // namespace fftc

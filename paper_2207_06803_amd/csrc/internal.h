@@ -55,14 +55,28 @@ constexpr int kSpecParts = 4;
 const SpecEntry* spec_part(int dtype, int part, int* count);
 const SpecEntry* find_spec(int dtype, int64_t n, const std::vector<int>& rs);
 
-struct TwSegment {
-    int64_t off;    // first entry in the table
-    int64_t count;  // entries
-    int64_t ns;     // entry idx -> a = idx / ns + 1, b = idx % ns
-    int64_t len;    // value = w_len^{(a b) mod len}
+// Two-pass column kernels with compiled bodies (fourstep_c64/c128.hip):
+// the four kernels (pass x direction) of one column length.
+struct FourStepEntry {
+    int dtype, len, nr;
+    int radices[kMaxStages];
+    int tpt, tc;
+    const void* fn[2][2];  // [pass - 1][inverse]
 };
-// Fill table[seg.off + idx] = exp(-2 pi i ((a b) mod len) / len) in fp64,
+const FourStepEntry* find_fourstep(int dtype, int64_t len, const std::vector<int>& rs);
+
+struct TwSegment {
+    int64_t off;      // first entry in the table
+    int64_t count;    // entries
+    int64_t ns;       // entry idx -> a = idx / ns + 1, b = idx % ns
+    int64_t len;      // value = w_len^{(mul a b) mod len}
+    int64_t mul = 1;
+};
+// Fill table[seg.off + idx] = exp(-2 pi i ((mul a b) mod len) / len) in fp64,
 // stored as float2 (rounded to nearest) or double2.
+// Two-pass plans: the factor w_N^e, e < N, is read as the product of
+// w_N^{e mod 1024} and w_N^{1024 (e div 1024)} from two small tables.
+constexpr int kTwSplit = 1024;
 fftc_status make_twiddles(void* table, int dtype, const std::vector<TwSegment>& segs,
                           hipStream_t stream);
 

@@ -39,14 +39,14 @@ struct MixedState {
     size_t lds_bytes = 0;
     void* dev = nullptr;  // one allocation: counter, classes, items, offsets, twiddles
     size_t dev_bytes = 0;
-    unsigned int* counter = nullptr;
+    unsigned int* counter = nullptr;  // [0] next item, [1] workgroups finished
     MixedClass* d_classes = nullptr;
     MixedItem* d_items = nullptr;
     int64_t* d_offsets = nullptr;
     void* d_tw = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t reset_node = nullptr, kernel_node = nullptr;
+    hipGraphNode_t kernel_node = nullptr;
     const void* fn = nullptr;
     MixedArgs args{};
     void* kargs[8] = {};

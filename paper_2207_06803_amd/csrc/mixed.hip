@@ -8,9 +8,9 @@
 // and LDS -- and are ordered by decreasing cost (longest processing time
 // first).  A grid sized to fill the GPU once pulls items from an atomic
 // counter until the list is exhausted; every workgroup leaves the loop after
-// reading an index past the end.  The counter is cleared by a small kernel in
-// front of the persistent kernel; both are recorded in a hipGraph at plan
-// time and relaunched per execution.
+// reading an index past the end, and the last one to leave clears the
+// counters for the next launch.  The launch is recorded in a hipGraph at plan
+// time and replayed per execution.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -19,10 +19,6 @@
 #include "plan.h"
 
 namespace fftc {
-
-__global__ void mixed_reset(unsigned int* counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
-}
 
 static const void* mixed_fn(int dtype, int direction) {
     const bool inv = direction == FFTC_INVERSE;
@@ -133,7 +129,7 @@ fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count) {
     // device block: counter | classes | items | offsets | twiddles
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t o_cnt = 0;
-    const size_t o_cls = align(o_cnt + sizeof(unsigned int));
+    const size_t o_cls = align(o_cnt + 2 * sizeof(unsigned int));
     const size_t o_items = align(o_cls + sizeof(MixedClass) * ncls);
     const size_t o_offs = align(o_items + sizeof(MixedItem) * sorted.size());
     const size_t o_tw = align(o_offs + sizeof(int64_t) * toffs.size());
@@ -149,7 +145,7 @@ fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count) {
     FFTC_HIP_TRY(hipMemcpy(m->d_classes, classes.data(), sizeof(MixedClass) * ncls, hipMemcpyHostToDevice));
     FFTC_HIP_TRY(hipMemcpy(m->d_items, sorted.data(), sizeof(MixedItem) * sorted.size(), hipMemcpyHostToDevice));
     FFTC_HIP_TRY(hipMemcpy(m->d_offsets, toffs.data(), sizeof(int64_t) * toffs.size(), hipMemcpyHostToDevice));
-    FFTC_HIP_TRY(hipMemset(m->counter, 0, sizeof(unsigned int)));
+    FFTC_HIP_TRY(hipMemset(m->counter, 0, 2 * sizeof(unsigned int)));
     fftc_status st = make_twiddles(m->d_tw, dtype, segs, nullptr);
     if (st != FFTC_OK) return st;
 
@@ -162,24 +158,13 @@ fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count) {
     FFTC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kMixedThreads, m->lds_bytes));
     m->groups = std::max(1, std::min(per_cu * cus, m->nitems));
 
-    // graph: reset counter -> persistent kernel
+    // graph: the persistent kernel (it leaves the counters cleared)
     FFTC_HIP_TRY(hipGraphCreate(&m->graph, 0));
-    {
-        hipKernelNodeParams kp{};
-        void* args[] = {&m->counter};
-        kp.func = reinterpret_cast<void*>(&mixed_reset);
-        kp.gridDim = dim3(1);
-        kp.blockDim = dim3(64);
-        kp.sharedMemBytes = 0;
-        kp.kernelParams = args;
-        kp.extra = nullptr;
-        FFTC_HIP_TRY(hipGraphAddKernelNode(&m->reset_node, m->graph, nullptr, 0, &kp));
-    }
     {
         m->args.in = nullptr;
         m->args.out = nullptr;
         hipKernelNodeParams kp = m->kernel_params(fn);
-        FFTC_HIP_TRY(hipGraphAddKernelNode(&m->kernel_node, m->graph, &m->reset_node, 1, &kp));
+        FFTC_HIP_TRY(hipGraphAddKernelNode(&m->kernel_node, m->graph, nullptr, 0, &kp));
     }
     FFTC_HIP_TRY(hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
     m->fn = fn;

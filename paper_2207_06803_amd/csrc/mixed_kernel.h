@@ -2,10 +2,12 @@
 // mixed_c64.hip / mixed_c128.hip, which supply the list of compiled bodies).
 //
 // Each resident workgroup loops: take the next item index from the atomic
-// counter, leave when it is past the end, otherwise run the item's
-// transforms with its class's body -- a compiled Stockham list when one
+// counter (counter[0]), leave when it is past the end, otherwise run the
+// item's transforms with its class's body -- a compiled Stockham list when one
 // exists, else the runtime-radix stages.  Threads beyond the class's
-// transforms only take part in the barriers.
+// transforms only take part in the barriers.  Every workgroup counts its exit
+// in counter[1]; the last one resets both counters, so consecutive launches
+// need no separate reset.
 #pragma once
 #include "mixed.h"
 #include "spec_table.h"
@@ -34,7 +36,14 @@ extern "C" __shared__ __align__(16) unsigned char fftc_dyn_lds[];
             __syncthreads();                                                                         \
             const int it = s_item;                                                                   \
             __syncthreads();                                                                         \
-            if (it >= nitems) break;                                                                 \
+            if (it >= nitems) {                                                                      \
+                /* the last workgroup out clears both counters for the next launch */               \
+                if (threadIdx.x == 0 && atomicAdd(counter + 1, 1u) == gridDim.x - 1) {               \
+                    atomicExch(counter, 0u);                                                         \
+                    atomicExch(counter + 1, 0u);                                                     \
+                }                                                                                    \
+                break;                                                                               \
+            }                                                                                        \
             const MixedItem item = items[it];                                                        \
             const MixedClass& c = classes[item.cls];                                                 \
             const GenDesc& d = c.desc;                                                               \

@@ -23,6 +23,8 @@ struct fftc_plan_s {
     int64_t m = 0, k = 0;
     fftc::GenDesc pass1{}, pass2{};  // length m (k columns), length k (m columns)
     std::vector<int> r1, r2;
+    const fftc::FourStepEntry* fs1 = nullptr;  // compiled column kernels, if any
+    const fftc::FourStepEntry* fs2 = nullptr;
     int64_t tw1_off = 0, tw2_off = 0, twn_off = 0;  // table offsets (elements)
     void* scratch = nullptr;  // two-pass in-place intermediate (absent: in place refused)
     size_t scratch_bytes = 0;

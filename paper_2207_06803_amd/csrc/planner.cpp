@@ -223,7 +223,7 @@ void tune_clear_all() {
 int64_t stage_segments(const std::vector<int>& rs, int64_t base, std::vector<TwSegment>* segs) {
     int64_t ns = 1, off = base;
     for (int r : rs) {
-        if (ns > 1) segs->push_back({off, (r - 1) * ns, ns, ns * r});
+        if (ns > 1) segs->push_back({off, (r - 1) * ns, ns, ns * r, 1});
         off += (r - 1) * ns;
         ns *= r;
     }

@@ -17,4 +17,20 @@ const SpecEntry* spec_part(int dtype, int part, int* count) {
     return dtype == FFTC_C128 ? c128[part](count) : c64[part](count);
 }
 
+const FourStepEntry* fourstep_table_c64(int* count);
+const FourStepEntry* fourstep_table_c128(int* count);
+
+const FourStepEntry* find_fourstep(int dtype, int64_t len, const std::vector<int>& rs) {
+    int cnt = 0;
+    const FourStepEntry* tab = dtype == FFTC_C128 ? fourstep_table_c128(&cnt) : fourstep_table_c64(&cnt);
+    for (int i = 0; i < cnt; ++i) {
+        const FourStepEntry& e = tab[i];
+        if (e.len != len || e.nr != (int)rs.size()) continue;
+        bool same = true;
+        for (int q = 0; q < e.nr; ++q) same = same && e.radices[q] == rs[q];
+        if (same) return &e;
+    }
+    return nullptr;
+}
+
 }  // namespace fftc
