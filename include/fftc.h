@@ -68,7 +68,8 @@ enum {
     FFTC_VARIANT_SINGLE_GENERIC = 1,     /* one kernel, runtime N and radix list */
     FFTC_VARIANT_TWO_PASS = 2,           /* Eq. 2 four-step in two kernels + scratch */
     FFTC_VARIANT_MIXED_PERSISTENT = 3,   /* mixed lengths, one persistent launch in a hipGraph */
-    FFTC_VARIANT_SPLIT_MFMA = 4          /* DFT_16 stages on the matrix cores (split precision) */
+    FFTC_VARIANT_SPLIT_MFMA = 4,         /* DFT_16 stages on the matrix cores (split precision) */
+    FFTC_VARIANT_FORMULA = 5             /* a Kronecker-product formula (fftc_plan_formula) */
 };
 
 typedef struct fftc_plan_s *fftc_plan_t;
@@ -126,9 +127,63 @@ typedef struct {
      * persistent workgroups */
     int64_t mixed_transforms, mixed_elements;
     int mixed_classes, mixed_items, persistent_groups;
+    /* formula plans: passes after lowering (0 when folded), 1 if the formula
+     * folded to I(p) (x) DFT(n) and runs as p batched transforms of the
+     * ordinary plan for n (then fold_n, fold_p), 1 if all passes run in one
+     * LDS-resident kernel */
+    int formula_passes, formula_folded, formula_lds;
+    int64_t formula_fold_n, formula_fold_p;
 } fftc_plan_desc;
 
 fftc_status fftc_plan_describe(fftc_plan_t plan, fftc_plan_desc *desc);
+
+/* ---------------------------------------------------------------------------
+ * Formula plans (Section IV-A: the DSL of Listing 1, grammar of Listing 2).
+ * A formula is a text such as
+ *     (DFT(2) (x) I(2)) . twiddle(4,2) . (I(2) (x) DFT(2)) . Permute(4,2)
+ * built from DFT(n), I(n), twiddle(N, M) = D^N_M and Permute(N, K) = Pi^N_K
+ * of Eq. 2, with (Pi^N_K x)[i M + j] = x[j K + i] (M = N / K) and D^N_M the
+ * diagonal w_N^{i j} at position i M + j.  Kronecker product: U+2297, "(x)"
+ * or "kron"; matrix product: U+00B7, ".", "*" or "@"; both group to the right at
+ * equal precedence (parentheses as needed); keywords are case-insensitive; a
+ * trailing identifier after a final product (the vector operand) is ignored.
+ * Sizes obey the shape rule (a Kronecker product multiplies them, a matrix
+ * product needs equal ones) and the whole formula is at most 2^24.
+ *
+ * The plan applies the formula's matrix F to `batch` contiguous vectors of
+ * length dim (batch * dim < 2^31): y = F x for FFTC_FORWARD and
+ * y = conj(F) x (for a DFT formula: the unscaled inverse) for FFTC_INVERSE.
+ * dtype: FFTC_C64 or FFTC_C128.  Unless FFTC_FORMULA_NO_FOLD is given, every
+ * four-factor window equal to Eq. 2 (or its transpose) folds back to DFT(N),
+ * and a formula that folds to I(p) (x) DFT(n) runs as the ordinary plan of
+ * n with p times the batch.  Everything else lowers to passes: DFT codelets,
+ * Stockham stages (or with FFTC_FORMULA_EQ2 the Eq. 2 factors themselves),
+ * direct sums for DFT sizes with prime factors > 7 (each such factor at most
+ * 16384), diagonals and permutations; with vectors of at most
+ * fftc_formula_max_lds_dim(dtype) elements they run in one kernel (unless
+ * FFTC_FORMULA_HBM_PASSES), else one kernel per pass with a plan-owned
+ * scratch buffer of batch * dim elements (executions of such plans must be
+ * ordered).  INVALID_ARG for a syntax or shape error or bad flags,
+ * UNSUPPORTED_SIZE when a factor cannot be lowered; the message names the
+ * place.
+ * ------------------------------------------------------------------------- */
+enum {
+    FFTC_FORMULA_NO_FOLD = 1,    /* keep the formula's own factors (no Eq. 2 folding) */
+    FFTC_FORMULA_EQ2 = 2,        /* DFT(n) factors lower to Eq. 2 (Pi, D, smaller DFTs) */
+    FFTC_FORMULA_HBM_PASSES = 4  /* one kernel per pass even when a vector fits LDS */
+};
+
+fftc_status fftc_plan_formula(const char *formula, int64_t batch, int direction, int dtype, int flags,
+                              fftc_plan_t *plan_out);
+
+/* Host-only: check and lower a formula without a GPU.  *dim = its size;
+ * text (capacity text_len, may be NULL) receives the folded formula and the
+ * pass list, one line each, NUL-terminated and truncated to fit. */
+fftc_status fftc_formula_lower(const char *formula, int flags, int dtype, int64_t *dim, char *text,
+                               size_t text_len);
+
+/* Largest vector length a formula plan runs in one LDS-resident kernel. */
+int64_t fftc_formula_max_lds_dim(int dtype);
 
 /*
  * Host-only: the radix list fftc_plan would choose for (n, dtype), without a

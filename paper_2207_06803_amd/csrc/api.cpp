@@ -305,6 +305,10 @@ static fftc_status execute_impl(fftc_plan_t p, const void* in, void* out, int64_
         return launch_mixed(p, in, out, s);
     }
     if (batch < 1 || batch > p->batch) return fail(FFTC_ERR_INVALID_ARG, "batch must be in [1, plan batch]");
+    if (p->variant == FFTC_VARIANT_FORMULA) {
+        if (p->inner) return execute_impl(p->inner, in, out, batch * p->fold_p, stream);
+        return formula_launch(p->formula, in, out, batch, p->direction == FFTC_INVERSE, s);
+    }
     if (p->variant == FFTC_VARIANT_SPLIT_MFMA) return launch_split(p, in, out, batch, s);
     if (p->variant == FFTC_VARIANT_TWO_PASS) return launch_two_pass(p, in, out, batch, s);
     return launch_single(p, in, out, batch, s);
@@ -330,6 +334,11 @@ fftc_status fftc_destroy_plan(fftc_plan_t p) {
         if (e != hipSuccess) st = fail_hip(e, "hipFree(scratch)");
     }
     if (p->mixed) destroy_mixed(p->mixed);
+    if (p->formula) formula_destroy(p->formula);
+    if (p->inner) {
+        fftc_status si = fftc_destroy_plan(p->inner);
+        if (st == FFTC_OK) st = si;
+    }
     delete p;
     return st;
 }
@@ -358,8 +367,96 @@ fftc_status fftc_plan_describe(fftc_plan_t p, fftc_plan_desc* d) {
         d->persistent_groups = p->mixed->groups;
         d->twiddle_bytes = p->mixed->dev_bytes;
     }
+    if (p->variant == FFTC_VARIANT_FORMULA) {
+        d->formula_passes = p->formula_passes;
+        d->formula_folded = p->inner ? 1 : 0;
+        d->formula_lds = p->formula_lds ? 1 : 0;
+        d->formula_fold_n = p->fold_n;
+        d->formula_fold_p = p->fold_p;
+        if (p->inner) {
+            d->nradices = (int)std::min<size_t>(p->inner->radices.size(), 16);
+            for (int i = 0; i < d->nradices; ++i) d->radices[i] = p->inner->radices[i];
+            d->split_m = p->inner->m;
+            d->split_k = p->inner->k;
+            d->twiddle_bytes = p->inner->tw_bytes;
+            d->scratch_bytes = p->inner->scratch_bytes;
+        }
+    }
     return FFTC_OK;
 }
+
+fftc_status fftc_plan_formula(const char* formula, int64_t batch, int direction, int dtype, int flags,
+                              fftc_plan_t* plan_out) {
+    try {
+        clear_error();
+        if (!plan_out) return fail(FFTC_ERR_INVALID_ARG, "plan_out is NULL");
+        *plan_out = nullptr;
+        if (!formula) return fail(FFTC_ERR_INVALID_ARG, "formula is NULL");
+        if (direction != FFTC_FORWARD && direction != FFTC_INVERSE)
+            return fail(FFTC_ERR_INVALID_ARG, "direction must be FFTC_FORWARD (-1) or FFTC_INVERSE (+1)");
+        if (dtype != FFTC_C64 && dtype != FFTC_C128)
+            return fail(FFTC_ERR_INVALID_ARG, "formula plans take FFTC_C64 or FFTC_C128");
+        if (batch < 1) return fail(FFTC_ERR_INVALID_ARG, "batch must be >= 1");
+        FormulaProgram prog;
+        fftc_status st = compile_formula(formula, flags, dtype, &prog);
+        if (st != FFTC_OK) return st;
+        if (batch >= (int64_t(1) << 31) / prog.dim)
+            return fail(FFTC_ERR_INVALID_ARG, "formula plans take batch * dim < 2^31 elements");
+        fftc_plan_s* p = new (std::nothrow) fftc_plan_s();
+        if (!p) return fail(FFTC_ERR_OUT_OF_MEMORY, "host allocation failed");
+        p->n = prog.dim;
+        p->batch = batch;
+        p->direction = direction;
+        p->dtype = dtype;
+        p->variant = FFTC_VARIANT_FORMULA;
+        hipGetDevice(&p->device);
+        if (prog.folded) {
+            p->fold_n = prog.fold_n;
+            p->fold_p = prog.fold_p;
+            st = plan_impl(prog.fold_n, batch * prog.fold_p, direction, dtype, nullptr, 0, &p->inner);
+        } else {
+            p->fold_p = 1;
+            p->formula_passes = (int)prog.passes.size();
+            st = formula_prepare(prog, dtype, batch, flags, &p->formula, &p->tw_bytes, &p->scratch_bytes);
+            if (st == FFTC_OK) p->formula_lds = p->scratch_bytes == 0;
+        }
+        if (st != FFTC_OK) {
+            std::string keep = t_last_error;
+            fftc_destroy_plan(p);
+            t_last_error = keep;
+            return st;
+        }
+        *plan_out = p;
+        return FFTC_OK;
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_plan_formula");
+    }
+}
+
+fftc_status fftc_formula_lower(const char* formula, int flags, int dtype, int64_t* dim, char* text,
+                               size_t text_len) {
+    try {
+        clear_error();
+        if (!formula || !dim) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
+        if (dtype != FFTC_C64 && dtype != FFTC_C128)
+            return fail(FFTC_ERR_INVALID_ARG, "formula plans take FFTC_C64 or FFTC_C128");
+        FormulaProgram prog;
+        fftc_status st = compile_formula(formula, flags, dtype, &prog);
+        if (st != FFTC_OK) return st;
+        *dim = prog.dim;
+        if (text && text_len) {
+            const std::string d = describe_formula(prog);
+            const size_t n = std::min(d.size(), text_len - 1);
+            memcpy(text, d.data(), n);
+            text[n] = 0;
+        }
+        return FFTC_OK;
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_formula_lower");
+    }
+}
+
+int64_t fftc_formula_max_lds_dim(int dtype) { return formula_lds_max_dim(dtype); }
 
 fftc_status fftc_factorize(int64_t n, int dtype, int* radices, int max_count, int* count, int64_t* split_m) {
     clear_error();

@@ -72,11 +72,7 @@ fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C*
 
 template <typename Real, int TC_, int N, int... Rs>
 struct FourStepInst {
-#ifdef FFTC_EXP_TC32
-    static constexpr int TC = N <= 512 ? 2 * TC_ : TC_;
-#else
     static constexpr int TC = TC_;
-#endif
     static constexpr int rs[sizeof...(Rs)] = {Rs...};
     static constexpr int TPT = round_tpt(required_tpt(N, rs, (int)sizeof...(Rs)));
     static_assert(TPT * TC <= 1024, "four-step tile too large");

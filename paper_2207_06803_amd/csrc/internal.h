@@ -68,9 +68,10 @@ const FourStepEntry* find_fourstep(int dtype, int64_t len, const std::vector<int
 struct TwSegment {
     int64_t off;      // first entry in the table
     int64_t count;    // entries
-    int64_t ns;       // entry idx -> a = idx / ns + 1, b = idx % ns
+    int64_t ns;       // entry idx -> a = idx / ns + a0, b = idx % ns
     int64_t len;      // value = w_len^{(mul a b) mod len}
     int64_t mul = 1;
+    int64_t a0 = 1;
 };
 // Fill table[seg.off + idx] = exp(-2 pi i ((mul a b) mod len) / len) in fp64,
 // stored as float2 (rounded to nearest) or double2.

@@ -2,6 +2,7 @@
 #pragma once
 #include <vector>
 
+#include "formula.h"
 #include "generic.h"
 #include "internal.h"
 #include "mixed.h"
@@ -30,6 +31,12 @@ struct fftc_plan_s {
     size_t scratch_bytes = 0;
     // mixed-length persistent plan
     fftc::MixedState* mixed = nullptr;
+    // formula plan: lowered passes, or the ordinary plan it folded to
+    fftc::FormulaExec* formula = nullptr;
+    fftc_plan_s* inner = nullptr;
+    int64_t fold_n = 0, fold_p = 0;
+    int formula_passes = 0;
+    bool formula_lds = false;
 };
 
 namespace fftc {

@@ -1,11 +1,13 @@
 // Twiddle tables, generated on the GPU in fp64.
 //
 // Each segment describes entries value(idx) = w_L^{(m a b) mod L} with
-// a = idx / ns + 1, b = idx mod ns and w_L = exp(-2 pi i / L).  For a
+// a = idx / ns + a0 (a0 = 1 unless stated), b = idx mod ns and
+// w_L = exp(-2 pi i / L).  For a
 // Stockham stage of radix R after Ns (the twiddle diagonal of Eq. 2 at
 // length Ns R) this is the [r - 1][k] table of w_{Ns R}^{r k}; with ns = L
 // it is the plain table w_L^b, and with a multiplier m the coarse table
-// w_L^{m b} of the two-pass plans.  The exponent is
+// w_L^{m b} of the two-pass plans; with a0 = 0 it is the diagonal D^L_ns
+// of Eq. 2 (entry i ns + j = w_L^{i j}).  The exponent is
 // reduced exactly in integers and the angle is taken in (-pi, pi] before
 // sincospi, so the quarter turns come out exact.  complex64 plans round
 // the fp64 value to nearest fp32.
@@ -14,7 +16,7 @@
 namespace fftc {
 
 struct TwSegDev {
-    int64_t off, count, ns, len, mul;
+    int64_t off, count, ns, len, mul, a0;
 };
 
 template <typename C>
@@ -22,7 +24,7 @@ __global__ void twiddle_kernel(C* table, const TwSegDev* __restrict__ segs) {
     const TwSegDev s = segs[blockIdx.y];
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < s.count;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t a = idx / s.ns + 1, b = idx % s.ns;
+        const int64_t a = idx / s.ns + s.a0, b = idx % s.ns;
         int64_t m = ((s.mul * a) % s.len) * b % s.len;
         if (2 * m > s.len) m -= s.len;  // angle in (-pi, pi]
         double sn, cs;
@@ -41,7 +43,7 @@ fftc_status make_twiddles(void* table, int dtype, const std::vector<TwSegment>& 
     std::vector<TwSegDev> h(segs.size());
     int64_t maxc = 1;
     for (size_t i = 0; i < segs.size(); ++i) {
-        h[i] = {segs[i].off, segs[i].count, segs[i].ns, segs[i].len, segs[i].mul};
+        h[i] = {segs[i].off, segs[i].count, segs[i].ns, segs[i].len, segs[i].mul, segs[i].a0};
         maxc = std::max<int64_t>(maxc, segs[i].count);
     }
     if (segs.size() > 65535) return fail(FFTC_ERR_INTERNAL, "too many twiddle segments");

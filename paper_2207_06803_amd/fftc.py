@@ -29,7 +29,12 @@ DTYPES = {"c64": C64, "complex64": C64, C64: C64, "c128": C128, "complex128": C1
           "f16": C64_F16, C64_F16: C64_F16}
 
 VARIANT_NAMES = {0: "single_specialised", 1: "single_generic", 2: "two_pass", 3: "mixed_persistent",
-                 4: "split_mfma"}
+                 4: "split_mfma", 5: "formula"}
+
+# formula plan flags
+FORMULA_NO_FOLD = 1
+FORMULA_EQ2 = 2
+FORMULA_HBM_PASSES = 4
 
 STATUS = {0: "FFTC_OK", 1: "FFTC_ERR_INVALID_ARG", 2: "FFTC_ERR_UNSUPPORTED_SIZE",
           3: "FFTC_ERR_OUT_OF_MEMORY", 4: "FFTC_ERR_TOO_LARGE", 5: "FFTC_ERR_HIP",
@@ -50,7 +55,10 @@ class PlanDesc(ctypes.Structure):
                 ("split_k", ctypes.c_int64), ("twiddle_bytes", ctypes.c_size_t),
                 ("scratch_bytes", ctypes.c_size_t), ("mixed_transforms", ctypes.c_int64),
                 ("mixed_elements", ctypes.c_int64), ("mixed_classes", ctypes.c_int),
-                ("mixed_items", ctypes.c_int), ("persistent_groups", ctypes.c_int)]
+                ("mixed_items", ctypes.c_int), ("persistent_groups", ctypes.c_int),
+                ("formula_passes", ctypes.c_int), ("formula_folded", ctypes.c_int),
+                ("formula_lds", ctypes.c_int), ("formula_fold_n", ctypes.c_int64),
+                ("formula_fold_p", ctypes.c_int64)]
 
 
 _i64, _int, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
@@ -58,6 +66,7 @@ _SIGNATURES = {
     "fftc_plan": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(_vp)]),
     "fftc_plan_radices": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(_int), _int, ctypes.POINTER(_vp)]),
     "fftc_execute": (_int, [_vp, _vp, _vp, _vp]),
+    "fftc_execute_batch": (_int, [_vp, _vp, _vp, _i64, _vp]),
     "fftc_destroy_plan": (_int, [_vp]),
     "fftc_plan_describe": (_int, [_vp, ctypes.POINTER(PlanDesc)]),
     "fftc_factorize": (_int, [_i64, _int, ctypes.POINTER(_int), _int, ctypes.POINTER(_int),
@@ -73,6 +82,10 @@ _SIGNATURES = {
     "fftc_tune_load": (_int, [ctypes.c_char_p, ctypes.POINTER(_int)]),
     "fftc_tune_save": (_int, [ctypes.c_char_p, ctypes.POINTER(_int)]),
     "fftc_tune_clear": (_int, []),
+    "fftc_plan_formula": (_int, [ctypes.c_char_p, _i64, _int, _int, _int, ctypes.POINTER(_vp)]),
+    "fftc_formula_lower": (_int, [ctypes.c_char_p, _int, _int, ctypes.POINTER(_i64), ctypes.c_char_p,
+                                  ctypes.c_size_t]),
+    "fftc_formula_max_lds_dim": (_i64, [_int]),
     "fftc_status_string": (ctypes.c_char_p, [_int]),
     "fftc_last_error": (ctypes.c_char_p, []),
 }
@@ -98,14 +111,33 @@ def _load() -> ctypes.CDLL:
     return lib
 
 
-lib = _load()
+class _Declared:
+    """The library with only its declared entry points visible: ctypes would
+    pass undeclared arguments as 32-bit ints (truncating device pointers)."""
+
+    def __init__(self, so: ctypes.CDLL):
+        self._so = so
+        self._fns = {name: getattr(so, name) for name in _SIGNATURES}
+
+    def declare(self, name: str, restype, argtypes) -> None:
+        fn = getattr(self._so, name)
+        fn.restype = restype
+        fn.argtypes = argtypes
+        self._fns[name] = fn
+
+    def __getattr__(self, name):
+        try:
+            return self.__dict__["_fns"][name]
+        except KeyError:
+            raise AttributeError(f"{name} has no declared signature; call fftc.register first") from None
+
+
+lib = _Declared(_load())
 
 
 def register(name: str, restype, argtypes) -> None:
     """Declare the signature of a further C entry point of the library."""
-    fn = getattr(lib, name)
-    fn.restype = restype
-    fn.argtypes = argtypes
+    lib.declare(name, restype, argtypes)
 
 
 def last_error() -> str:
@@ -173,6 +205,11 @@ class Plan:
         """Enqueue y = DFT(x) on the stream (default: torch's current stream)."""
         check(lib.fftc_execute(self._h, ptr(x), ptr(y), stream_handle(stream)), "fftc_execute")
 
+    def execute_batch(self, x, y, batch: int, stream=None) -> None:
+        """Enqueue the first `batch` transforms (1 <= batch <= the plan's batch)."""
+        check(lib.fftc_execute_batch(self._h, ptr(x), ptr(y), int(batch), stream_handle(stream)),
+              "fftc_execute_batch")
+
     def describe(self) -> dict:
         d = PlanDesc()
         check(lib.fftc_plan_describe(self._h, ctypes.byref(d)), "fftc_plan_describe")
@@ -185,7 +222,10 @@ class Plan:
                 "twiddle_bytes": d.twiddle_bytes, "scratch_bytes": d.scratch_bytes,
                 "mixed_transforms": d.mixed_transforms, "mixed_elements": d.mixed_elements,
                 "mixed_classes": d.mixed_classes, "mixed_items": d.mixed_items,
-                "persistent_groups": d.persistent_groups}
+                "persistent_groups": d.persistent_groups,
+                "formula_passes": d.formula_passes, "formula_folded": bool(d.formula_folded),
+                "formula_lds": bool(d.formula_lds), "formula_fold_n": d.formula_fold_n,
+                "formula_fold_p": d.formula_fold_p}
 
     def close(self) -> None:
         if self._h is not None and self._h.value:
@@ -217,6 +257,33 @@ def plan_mixed(lengths, direction: int = FORWARD, dtype="c64") -> Plan:
     p = Plan(0, len(lens), direction, dtype, _handle=h)
     p.lengths = lens
     return p
+
+
+def plan_formula(formula: str, batch: int, direction: int = FORWARD, dtype="c64", flags: int = 0) -> Plan:
+    """Plan applying a Kronecker-product formula (the DSL of the paper's
+    Section IV-A) to `batch` contiguous vectors of its size."""
+    h = _vp()
+    check(lib.fftc_plan_formula(formula.encode(), batch, direction, dtype_code(dtype), flags,
+                                ctypes.byref(h)), "fftc_plan_formula")
+    d = PlanDesc()
+    check(lib.fftc_plan_describe(h, ctypes.byref(d)), "fftc_plan_describe")
+    p = Plan(int(d.n), batch, direction, dtype, _handle=h)
+    p.formula = formula
+    return p
+
+
+def formula_lower(formula: str, flags: int = 0, dtype="c64"):
+    """Host only: (size, lowering text) of a formula -- the folded formula and
+    its pass list; raises FFTCError on a syntax or shape error."""
+    dim = _i64()
+    buf = ctypes.create_string_buffer(1 << 16)
+    check(lib.fftc_formula_lower(formula.encode(), flags, dtype_code(dtype), ctypes.byref(dim), buf,
+                                 len(buf)), "fftc_formula_lower")
+    return dim.value, buf.value.decode()
+
+
+def formula_max_lds_dim(dtype="c64") -> int:
+    return int(lib.fftc_formula_max_lds_dim(dtype_code(dtype)))
 
 
 def autotune(n: int, batch: int, dtype="c64", reps: int = 10):

@@ -1,0 +1,177 @@
+"""Formula plans on the GPU against the formula oracle (oracle/formula.py)
+and the FP64 DFT oracle: every pass kind, both execution paths (one
+LDS-resident kernel, one HBM kernel per pass), both directions, ragged
+batches, in place, and folded formulas."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.formula as of
+from gpu_util import np_dtype, rel_l2, say, tol_for
+from paper_2207_06803_amd import formulas, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2207_06803_amd import fftc  # noqa: E402
+
+FWD, INV = fftc.FORWARD, fftc.INVERSE
+NO_FOLD, EQ2, HBM = fftc.FORMULA_NO_FOLD, fftc.FORMULA_EQ2, fftc.FORMULA_HBM_PASSES
+
+
+def run(plan, x, inplace=False):
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    yd = xd if inplace else torch.empty_like(xd)
+    plan.execute(xd, yd)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+def tol(text, dim, dtype):
+    # DFT sizes with a prime factor above 7 are summed directly: the fp32
+    # error of a sum of s terms grows like sqrt(s) eps
+    base = tol_for(dim, dtype)
+    big = [int(t.split(")")[0]) for t in text.split("DFT(")[1:]]
+    s = max([1] + [v for v in big if any(v % p == 0 for p in (11, 13, 17, 19, 23, 29, 31, 37, 41, 43))])
+    return base * max(1.0, math.sqrt(s) / 2)
+
+
+FORMULAS = [
+    formulas.recursive_ct(4),
+    formulas.recursive_ct(64, (2,)),
+    formulas.recursive_ct(48, (4, 3)),
+    formulas.recursive_dif(40, (5, 2)),
+    formulas.recursive_ct(1024, (4,)),
+    formulas.dft2d(8, 12),
+    formulas.dft2d(64, 64),
+    formulas.four_step_no_transpose(8, 16),
+    "DFT(22)", "DFT(13) ⊗ I(3)", "I(2) ⊗ DFT(26) ⊗ I(2)", "DFT(96)", "DFT(11) ⊗ DFT(7)",
+    "DFT(16) ⊗ DFT(3) ⊗ DFT(5) ⊗ DFT(7)",
+    "Permute(24, 4) · (I(4) ⊗ twiddle(6, 2)) · (DFT(4) ⊗ I(6))",
+    "(DFT(2) ⊗ Permute(6, 2)) · (twiddle(6, 3) ⊗ I(2)) · (I(3) ⊗ DFT(4))",
+    "I(5)", "twiddle(36, 6) · Permute(36, 6)", "DFT(127)",
+]
+
+
+@pytest.mark.parametrize("flags", [NO_FOLD, NO_FOLD | EQ2, NO_FOLD | HBM, NO_FOLD | EQ2 | HBM])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("text", FORMULAS)
+def test_formula_vs_oracle(text, dtype, flags):
+    dim = of.size(of.parse(text))
+    b = 5 if dim <= 4096 else 2
+    x = synth.uniform_complex(synth.rng(120, dim % 1009, flags), (b, dim), np_dtype(dtype))
+    for d in (FWD, INV):
+        say(f"formula {text[:60]!r} dim={dim} {dtype} flags={flags} dir={d}")
+        with fftc.plan_formula(text, b, d, dtype, flags) as p:
+            desc = p.describe()
+            assert desc["variant"] == "formula" and desc["n"] == dim
+            assert desc["formula_lds"] == (not (flags & HBM) and dim <= fftc.formula_max_lds_dim(dtype))
+            y = run(p, x)
+            y_in = run(p, x, inplace=True)
+        want = of.apply(text, x, d)
+        err = rel_l2(y, want)
+        assert err.max() <= tol(text, dim, dtype), (err.max(), desc)
+        assert np.array_equal(y, y_in)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_listing1_program(dtype):
+    # createComplex([1,2,3,4], [1,2,3,4]) through the Listing 1 formula: small
+    # integers, every operation exact in either precision
+    text = formulas.recursive_ct(4) + " · InputComplex"
+    x = np.array([[1 + 1j, 2 + 2j, 3 + 3j, 4 + 4j]], dtype=np_dtype(dtype))
+    for flags in (0, NO_FOLD, NO_FOLD | HBM):
+        with fftc.plan_formula(text, 1, FWD, dtype, flags) as p:
+            assert p.describe()["formula_folded"] == (flags == 0)
+            y = run(p, x)
+        assert np.array_equal(y[0], np.array([10 + 10j, -4, -2 - 2j, -4j])), (flags, y)
+
+
+@pytest.mark.parametrize("n,rs,dtype", [(1024, (2,), "c64"), (4096, (4,), "c64"), (256, (2,), "c128"),
+                                        (3 * 5 * 7 * 8, (8, 7, 5, 3), "c64"), (32768, (8,), "c64")])
+def test_folded_recursive_ct_runs_the_plan(n, rs, dtype):
+    b = 3
+    x = synth.uniform_complex(synth.rng(121, n % 997), (b, n), np_dtype(dtype))
+    for text in (formulas.recursive_ct(n, rs), formulas.recursive_dif(n, rs)):
+        for d in (FWD, INV):
+            with fftc.plan_formula(text, b, d, dtype) as p:
+                desc = p.describe()
+                assert desc["formula_folded"] and desc["formula_fold_n"] == n and desc["formula_fold_p"] == 1
+                y = run(p, x)
+            with fftc.Plan(n, b, d, dtype) as q:
+                y_plan = run(q, x)
+            assert np.array_equal(y, y_plan)
+            assert rel_l2(y, oracle.dft(x, d)).max() <= tol_for(n, dtype)
+
+
+def test_folded_batched_identity_kron():
+    n, p_, b = 512, 6, 4
+    text = f"I({p_}) ⊗ ({formulas.recursive_ct(n, (8,))})"
+    x = synth.uniform_complex(synth.rng(122), (b, p_ * n), np.complex64)
+    with fftc.plan_formula(text, b, FWD, "c64") as p:
+        desc = p.describe()
+        assert desc["formula_folded"] and desc["formula_fold_p"] == p_
+        y = run(p, x)
+    want = oracle.dft(x.reshape(b * p_, n)).reshape(b, p_ * n)
+    assert rel_l2(y, want).max() <= tol_for(n, "c64")
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_hbm_path_beyond_lds(dtype):
+    # 128 x 128 2-D DFT (16384 > the LDS limit) and a 2^16 Eq. 2 program without folding
+    for text in (formulas.dft2d(128, 128), formulas.recursive_ct(1 << 16, (16,))):
+        dim = of.size(of.parse(text))
+        x = synth.uniform_complex(synth.rng(123, dim % 1013), (2, dim), np_dtype(dtype))
+        for flags in (NO_FOLD, NO_FOLD | EQ2):
+            with fftc.plan_formula(text, 2, FWD, dtype, flags) as p:
+                desc = p.describe()
+                assert not desc["formula_lds"] and desc["scratch_bytes"] == 2 * dim * x.itemsize
+                y = run(p, x)
+                y_in = run(p, x, inplace=True)
+            if text.startswith("DFT(128)"):
+                want = of.apply(text, x)
+            else:
+                want = oracle.dft(x)
+            assert rel_l2(y, want).max() <= tol_for(dim, dtype), (text[:40], flags)
+            assert np.array_equal(y, y_in)
+
+
+def test_partial_batches_and_ragged_tiles():
+    # dim 12: 341 vectors per LDS tile; batches that end mid-tile
+    text = "Permute(12, 3) · (I(3) ⊗ DFT(4)) · twiddle(12, 4) · (DFT(3) ⊗ I(4))"
+    b = 1000
+    x = synth.uniform_complex(synth.rng(124), (b, 12), np.complex64)
+    want = of.apply(text, x)
+    with fftc.plan_formula(text, b, FWD, "c64", NO_FOLD) as p:
+        for nb in (1, 340, 341, 342, 999, 1000):
+            xd = torch.from_numpy(x[:nb].copy()).cuda()
+            yd = torch.full_like(xd, complex(7, 7))
+            p.execute_batch(xd, yd, nb)
+            torch.cuda.synchronize()
+            y = yd.cpu().numpy()
+            assert rel_l2(y, want[:nb]).max() <= tol_for(12, "c64"), nb
+
+
+def test_determinism():
+    text = formulas.dft2d(64, 64)
+    x = synth.uniform_complex(synth.rng(125), (8, 4096), np.complex64)
+    with fftc.plan_formula(text, 8, FWD, "c64", NO_FOLD) as p:
+        y0 = run(p, x)
+        y1 = run(p, x)
+    with fftc.plan_formula(text, 3, FWD, "c64", NO_FOLD) as p:
+        y2 = run(p, x[:3])
+    assert np.array_equal(y0, y1) and np.array_equal(y0[:3], y2)
+
+
+def test_plan_errors():
+    with pytest.raises(fftc.FFTCError):
+        fftc.plan_formula("DFT(4) · DFT(2)", 1)
+    with pytest.raises(fftc.FFTCError):
+        fftc.plan_formula("DFT(4)", 0)
+    with pytest.raises(fftc.FFTCError):
+        fftc.plan_formula("DFT(1048576) ⊗ I(2)", 1 << 11)  # batch * dim >= 2^31
