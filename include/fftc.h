@@ -130,9 +130,10 @@ typedef struct {
     /* formula plans: passes after lowering (0 when folded), 1 if the formula
      * folded to I(p) (x) DFT(n) and runs as p batched transforms of the
      * ordinary plan for n (then fold_n, fold_p), 1 if all passes run in one
-     * LDS-resident kernel */
+     * LDS-resident kernel, kernels launched per execution (0 when folded) */
     int formula_passes, formula_folded, formula_lds;
     int64_t formula_fold_n, formula_fold_p;
+    int formula_kernels;
 } fftc_plan_desc;
 
 fftc_status fftc_plan_describe(fftc_plan_t plan, fftc_plan_desc *desc);
@@ -160,10 +161,13 @@ fftc_status fftc_plan_describe(fftc_plan_t plan, fftc_plan_desc *desc);
  * Stockham stages (or with FFTC_FORMULA_EQ2 the Eq. 2 factors themselves),
  * direct sums for DFT sizes with prime factors > 7 (each such factor at most
  * 16384), diagonals and permutations; with vectors of at most
- * fftc_formula_max_lds_dim(dtype) elements they run in one kernel (unless
- * FFTC_FORMULA_HBM_PASSES), else one kernel per pass with a plan-owned
- * scratch buffer of batch * dim elements (executions of such plans must be
- * ordered).  INVALID_ARG for a syntax or shape error or bad flags,
+ * fftc_formula_max_lds_dim(dtype) elements they run in one kernel.  Longer
+ * vectors run in as few kernels as the passes allow: consecutive passes
+ * I_p (x) E (x) I_q whose common factors P0 | p, Q0 | q leave sub-vectors of
+ * dim / (P0 Q0) <= that limit run together in LDS; a pass that touches more
+ * elements runs alone over HBM.  FFTC_FORMULA_HBM_PASSES runs every pass as
+ * its own HBM kernel.  Plans of more than one kernel own a scratch buffer
+ * of batch * dim elements (their executions must be ordered).  INVALID_ARG for a syntax or shape error or bad flags,
  * UNSUPPORTED_SIZE when a factor cannot be lowered; the message names the
  * place.
  * ------------------------------------------------------------------------- */

@@ -371,6 +371,7 @@ fftc_status fftc_plan_describe(fftc_plan_t p, fftc_plan_desc* d) {
         d->formula_passes = p->formula_passes;
         d->formula_folded = p->inner ? 1 : 0;
         d->formula_lds = p->formula_lds ? 1 : 0;
+        d->formula_kernels = p->inner ? 0 : p->formula_kernels;
         d->formula_fold_n = p->fold_n;
         d->formula_fold_p = p->fold_p;
         if (p->inner) {
@@ -417,8 +418,9 @@ fftc_status fftc_plan_formula(const char* formula, int64_t batch, int direction,
         } else {
             p->fold_p = 1;
             p->formula_passes = (int)prog.passes.size();
-            st = formula_prepare(prog, dtype, batch, flags, &p->formula, &p->tw_bytes, &p->scratch_bytes);
-            if (st == FFTC_OK) p->formula_lds = p->scratch_bytes == 0;
+            st = formula_prepare(prog, dtype, batch, flags, &p->formula, &p->tw_bytes, &p->scratch_bytes,
+                                 &p->formula_kernels);
+            if (st == FFTC_OK) p->formula_lds = p->scratch_bytes == 0;  // one LDS-resident kernel
         }
         if (st != FFTC_OK) {
             std::string keep = t_last_error;

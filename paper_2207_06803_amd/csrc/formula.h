@@ -50,8 +50,9 @@ std::string describe_formula(const FormulaProgram& prog);
 
 // ---- execution (formula.hip) ----------------------------------------------
 struct FormulaExec;  // device pass list, table and launch shape
+// kernels: launches per execution (1: the whole formula in one LDS kernel).
 fftc_status formula_prepare(const FormulaProgram& prog, int dtype, int64_t batch, int flags,
-                            FormulaExec** out, size_t* table_bytes, size_t* scratch_bytes);
+                            FormulaExec** out, size_t* table_bytes, size_t* scratch_bytes, int* kernels);
 fftc_status formula_launch(FormulaExec* fx, const void* in, void* out, int64_t batch, bool inverse,
                            hipStream_t s);
 void formula_destroy(FormulaExec* fx);

@@ -35,7 +35,7 @@ struct fftc_plan_s {
     fftc::FormulaExec* formula = nullptr;
     fftc_plan_s* inner = nullptr;
     int64_t fold_n = 0, fold_p = 0;
-    int formula_passes = 0;
+    int formula_passes = 0, formula_kernels = 0;
     bool formula_lds = false;
 };
 

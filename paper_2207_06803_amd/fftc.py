@@ -58,7 +58,7 @@ class PlanDesc(ctypes.Structure):
                 ("mixed_items", ctypes.c_int), ("persistent_groups", ctypes.c_int),
                 ("formula_passes", ctypes.c_int), ("formula_folded", ctypes.c_int),
                 ("formula_lds", ctypes.c_int), ("formula_fold_n", ctypes.c_int64),
-                ("formula_fold_p", ctypes.c_int64)]
+                ("formula_fold_p", ctypes.c_int64), ("formula_kernels", ctypes.c_int)]
 
 
 _i64, _int, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
@@ -225,7 +225,7 @@ class Plan:
                 "persistent_groups": d.persistent_groups,
                 "formula_passes": d.formula_passes, "formula_folded": bool(d.formula_folded),
                 "formula_lds": bool(d.formula_lds), "formula_fold_n": d.formula_fold_n,
-                "formula_fold_p": d.formula_fold_p}
+                "formula_fold_p": d.formula_fold_p, "formula_kernels": d.formula_kernels}
 
     def close(self) -> None:
         if self._h is not None and self._h.value:

@@ -71,6 +71,8 @@ def test_formula_vs_oracle(text, dtype, flags):
             desc = p.describe()
             assert desc["variant"] == "formula" and desc["n"] == dim
             assert desc["formula_lds"] == (not (flags & HBM) and dim <= fftc.formula_max_lds_dim(dtype))
+            if flags & HBM:
+                assert desc["formula_kernels"] == desc["formula_passes"], desc
             y = run(p, x)
             y_in = run(p, x, inplace=True)
         want = of.apply(text, x, d)
@@ -131,6 +133,10 @@ def test_hbm_path_beyond_lds(dtype):
             with fftc.plan_formula(text, 2, FWD, dtype, flags) as p:
                 desc = p.describe()
                 assert not desc["formula_lds"] and desc["scratch_bytes"] == 2 * dim * x.itemsize
+                if text.startswith("DFT(128)"):
+                    # rows then columns: two LDS runs of 128-element sub-vectors
+                    assert desc["formula_kernels"] == 2, desc
+                assert desc["formula_kernels"] < desc["formula_passes"], desc
                 y = run(p, x)
                 y_in = run(p, x, inplace=True)
             if text.startswith("DFT(128)"):
@@ -139,6 +145,35 @@ def test_hbm_path_beyond_lds(dtype):
                 want = oracle.dft(x)
             assert rel_l2(y, want).max() <= tol_for(dim, dtype), (text[:40], flags)
             assert np.array_equal(y, y_in)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_runs_of_strided_subvectors(dtype):
+    # vectors beyond the LDS limit whose passes group into runs with inner
+    # strides Q0 that are not multiples of 16 (tile columns Cc < 16)
+    cap = fftc.formula_max_lds_dim(dtype)
+    for text in ("DFT(2048) ⊗ DFT(12)", "DFT(24) ⊗ DFT(1536)", "(DFT(9) ⊗ I(3000)) · (I(9) ⊗ DFT(3000))",
+                 "DFT(5) ⊗ I(7) ⊗ DFT(600)"):
+        dim = of.size(of.parse(text))
+        assert dim > cap
+        b = 3
+        x = synth.uniform_complex(synth.rng(126, dim % 1019), (b, dim), np_dtype(dtype))
+        for d in (FWD, INV):
+            say(f"runs {text} {dtype} dir={d}")
+            with fftc.plan_formula(text, b, d, dtype, NO_FOLD) as p:
+                desc = p.describe()
+                assert 1 < desc["formula_kernels"] < desc["formula_passes"], desc
+                y = run(p, x)
+                y_in = run(p, x, inplace=True)
+                xd = torch.from_numpy(x).cuda()
+                yd = torch.zeros_like(xd)
+                p.execute_batch(xd, yd, 1)
+                torch.cuda.synchronize()
+                y1 = yd.cpu().numpy()
+            want = of.apply(text, x, d)
+            assert rel_l2(y, want).max() <= tol(text, dim, dtype), text
+            assert np.array_equal(y, y_in)
+            assert np.array_equal(y1[0], y[0]) and not y1[1:].any()
 
 
 def test_partial_batches_and_ragged_tiles():
