@@ -16,6 +16,8 @@ HIP events on the stream its kernels run on):
   * split-precision MFMA modes at N = 1024, 4096, 16384, batch 8192: time and
     error against the complex128 GPU path
   * serving: 20,000 Poisson-arriving requests, p50/p99 latency
+  * formula plans (the Kronecker-product DSL): Eq. 2 programs folded onto
+    the Stockham plans vs run as written, and 2-D DFT formulas
 and the FP64 oracle timed on the host cores as the CPU baseline.
 
 Prints one JSON line.  `value` is GFLOP/s in the 5 N log2 N convention.
@@ -57,6 +59,9 @@ def parse():
                     help="only run plain 128 MiB device copies (counter calibration)")
     ap.add_argument("--rocpd-summary", nargs="+", metavar="DB",
                     help="print per-kernel durations and counters from rocprofv3 databases, then exit")
+    ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="write profiles/hbm_traffic.json from FETCH_SIZE / WRITE_SIZE runs of the headline "
+                         "and of --calibrate-copy, then exit")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=10000.0)
     return ap.parse_args()
@@ -86,14 +91,20 @@ class Timer:
         return e0.elapsed_time(e1) / reps
 
 
+# Sources that determine the headline kernels' code, launch shape and radix
+# choice: a counter summary applies while these are unchanged.
+HEADLINE_SOURCES = ("codelets.h", "cplx.h", "kconfig.h", "stockham.h", "spec_table.h", "spec_list.inc",
+                    "spec_c64_p0.hip", "spec_c64_p1.hip", "spec_c64_p2.hip", "spec_c64_p3.hip",
+                    "exec.hip", "planner.cpp")
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2207_06803_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".inc", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in HEADLINE_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -297,6 +308,39 @@ def config4(torch, fftc, synth, timer):
                         "per transform against the complex128 GPU path", "by_n": out}
 
 
+def formula(torch, fftc, synth, timer):
+    """Formula plans at 2^24 complex64 elements per launch."""
+    from paper_2207_06803_amd import formulas as F
+    xs = [torch.from_numpy(synth.uniform_complex(synth.rng(6), (ELEMS,), np.complex64)).to("cuda")
+          for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    NF, EQ2 = fftc.FORMULA_NO_FOLD, fftc.FORMULA_EQ2
+    cases = [
+        ("listing1_folded", F.recursive_ct(4), 0), ("listing1_as_written", F.recursive_ct(4), NF),
+        ("recursive_ct_1024_r2_folded", F.recursive_ct(1024, (2,)), 0),
+        ("recursive_ct_1024_r2_as_written", F.recursive_ct(1024, (2,)), NF),
+        ("recursive_ct_1024_r16_as_written", F.recursive_ct(1024, (16, 4)), NF),
+        ("dft_1024_stockham_passes", "DFT(1024)", NF), ("dft_1024_eq2_passes", "DFT(1024)", NF | EQ2),
+        ("dft2d_32x32", F.dft2d(32, 32), 0), ("dft2d_64x64", F.dft2d(64, 64), 0),
+        ("dft2d_128x128", F.dft2d(128, 128), 0), ("dft2d_1024x1024", F.dft2d(1024, 1024), 0),
+    ]
+    out = {}
+    for name, text, flags in cases:
+        dim = fftc.formula_lower(text, flags)[0]
+        with fftc.plan_formula(text, ELEMS // dim, fftc.FORWARD, "c64", flags) as p:
+            d = p.describe()
+            avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % 2], ys[i % 2], timer.s), 10)
+        out[name] = {"dim": dim, "us": avg * 1e3, "hbm_gbs_algorithmic": 16.0 * ELEMS / (avg * 1e-3) / 1e9,
+                     "folded": d["formula_folded"], "passes": d["formula_passes"],
+                     "kernels": 1 if d["formula_folded"] else d["formula_kernels"]}
+    with fftc.Plan(1024, ELEMS // 1024, fftc.FORWARD, "c64") as p:
+        out["plan_1024_reference_us"] = timer.avg_ms(lambda i: p.execute(xs[i % 2], ys[i % 2], timer.s), 10) * 1e3
+    del xs, ys
+    torch.cuda.empty_cache()
+    return {"workload": "complex64 forward, 2^24 elements per launch; algorithmic bytes = one read and one "
+                        "write of every element", "cases": out}
+
+
 def config5(args, torch, fftc, synth):
     from paper_2207_06803_amd import server as srv
     g = synth.rng(5)
@@ -409,10 +453,57 @@ def rocpd_summary(paths):
         print()
 
 
+def _counter_means(path, counter):
+    import re
+    import sqlite3
+    db = sqlite3.connect(path)
+    agg = {}
+    for name, cn, val in db.execute("select kernel_name, counter_name, value from counters_collection"):
+        if cn == counter:
+            agg.setdefault(re.sub(r"[(].*", "", name), []).append(val)
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def traffic_json(fetch_db, write_db, copy_fetch_db, copy_write_db):
+    """Calibrated HBM bytes per launch of the headline kernels: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) scaled by what they read for a plain copy of
+    2^24 complex64 (128 MiB read, 128 MiB written)."""
+    import re
+    cf, cw = _counter_means(copy_fetch_db, "FETCH_SIZE"), _counter_means(copy_write_db, "WRITE_SIZE")
+    copy_name = max(cf, key=cf.get)
+    kib = 8.0 * ELEMS / 1024
+    fscale, wscale = kib / cf[copy_name], kib / cw[copy_name]
+    fetch, write = _counter_means(fetch_db, "FETCH_SIZE"), _counter_means(write_db, "WRITE_SIZE")
+    kernels = {}
+    for name in fetch:
+        m = re.search(r"SpecCfg<float, (\d+), \d+, \d+, (true|false)>", name)
+        if not m or name not in write:
+            continue
+        key = f"c64_{m.group(1)}_{'inv' if m.group(2) == 'true' else 'fwd'}"
+        b = (fetch[name] * fscale + write[name] * wscale) * 1024
+        kernels[key] = {"kernel": name, "fetch_kib_raw": round(fetch[name], 1), "write_kib_raw": round(write[name], 1),
+                        "bytes_per_launch": int(round(b)), "algorithmic_bytes": 16 * ELEMS,
+                        "ratio_to_algorithmic": round(b / (16 * ELEMS), 5)}
+    out = {"source_hash": source_hash(), "sources": list(HEADLINE_SOURCES),
+           "calibration": {"kernel": f"{copy_name} (torch copy_ of 2^24 complex64)", "bytes_read": 8 * ELEMS,
+                           "bytes_written": 8 * ELEMS, "fetch_kib_raw": round(cf[copy_name], 1),
+                           "write_kib_raw": round(cw[copy_name], 1), "fetch_scale": round(fscale, 5),
+                           "write_scale": round(wscale, 5)},
+           "kernels": dict(sorted(kernels.items()))}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
+
+
 def main():
     args = parse()
     if args.rocpd_summary:
         rocpd_summary(args.rocpd_summary)
+        return
+    if args.traffic_json:
+        traffic_json(*args.traffic_json)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
@@ -449,6 +540,7 @@ def main():
                          ("two_pass", lambda: two_pass(torch, fftc, synth, timer)),
                          ("config3_mixed", lambda: config3(torch, fftc, synth, timer)),
                          ("config4_split_precision", lambda: config4(torch, fftc, synth, timer)),
+                         ("formula", lambda: formula(torch, fftc, synth, timer)),
                          ("config5_serving", lambda: config5(args, torch, fftc, synth))):
             log(f"{name} ...")
             extras[name] = fn()
