@@ -92,19 +92,27 @@ class Timer:
 
 
 # Sources that determine the headline kernels' code, launch shape and radix
-# choice: a counter summary applies while these are unchanged.
-HEADLINE_SOURCES = ("codelets.h", "cplx.h", "kconfig.h", "stockham.h", "spec_table.h", "spec_list.inc",
-                    "spec_c64_p0.hip", "spec_c64_p1.hip", "spec_c64_p2.hip", "spec_c64_p3.hip",
-                    "exec.hip", "planner.cpp")
+# choice: a counter summary applies while these are unchanged.  Of the
+# generated list of compiled kernels only the complex64 entries of the
+# headline lengths count (without their ids, which shift when other lengths
+# are added).
+HEADLINE_SOURCES = ("codelets.h", "cplx.h", "kconfig.h", "stockham.h", "spec_table.h", "exec.hip", "planner.cpp")
 
 
 def source_hash():
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2207_06803_amd", "csrc")
     for name in HEADLINE_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
+    with open(os.path.join(csrc, "spec_list.inc")) as f:
+        text = f.read()
+    c64 = text.split("FFTC_SPEC_LIST_C128")[0]
+    for n in SIZES:
+        for m in re.finditer(r"X\(\d+, (%d(?:, \d+)+)\)" % n, c64):
+            h.update(m.group(1).encode())
     return h.hexdigest()[:16]
 
 
@@ -484,7 +492,8 @@ def traffic_json(fetch_db, write_db, copy_fetch_db, copy_write_db):
         kernels[key] = {"kernel": name, "fetch_kib_raw": round(fetch[name], 1), "write_kib_raw": round(write[name], 1),
                         "bytes_per_launch": int(round(b)), "algorithmic_bytes": 16 * ELEMS,
                         "ratio_to_algorithmic": round(b / (16 * ELEMS), 5)}
-    out = {"source_hash": source_hash(), "sources": list(HEADLINE_SOURCES),
+    out = {"source_hash": source_hash(),
+           "sources": list(HEADLINE_SOURCES) + ["spec_list.inc (complex64 lists of N = %s)" % ", ".join(map(str, SIZES))],
            "calibration": {"kernel": f"{copy_name} (torch copy_ of 2^24 complex64)", "bytes_read": 8 * ELEMS,
                            "bytes_written": 8 * ELEMS, "fetch_kib_raw": round(cf[copy_name], 1),
                            "write_kib_raw": round(cw[copy_name], 1), "fetch_scale": round(fscale, 5),
