@@ -107,6 +107,47 @@ fftc_status fftc_execute(fftc_plan_t plan, const void *in, void *out, void *stre
  * plan's batch); in and out hold batch * n elements.  Not for mixed plans. */
 fftc_status fftc_execute_batch(fftc_plan_t plan, const void *in, void *out, int64_t batch, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Data layouts (planar and strided).  The DSL of the paper's Section IV-A
+ * builds its complex input from separate real and imaginary arrays
+ * (createComplex of Listing 1); libraries also transform data that is not
+ * contiguous.  A layout says where element j of transform b is:
+ *     interleaved:  ptr[b dist + j stride]            (complex elements)
+ *     planar:       re[b dist + j stride], im[b dist + j stride]   (reals)
+ * stride >= 1, dist >= 1, in elements.  The transforms of a layout must not
+ * share elements: either dist >= (n - 1) stride + 1 (one block per
+ * transform) or stride >= batch dist (transforms interleaved element by
+ * element, e.g. the columns of a row-major array).  The layout is applied in
+ * the first stage's loads and the last stage's stores of the same Stockham
+ * kernels (no extra pass over HBM).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t stride;  /* elements between consecutive points of one transform */
+    int64_t dist;    /* elements between the first points of consecutive transforms */
+    int planar;      /* 0: interleaved complex; 1: separate real and imaginary arrays */
+} fftc_layout;
+
+/*
+ * Plan for `batch` transforms of length n reading the `in` layout and
+ * writing the `out` layout (NULL = interleaved, stride 1, dist n).
+ * complex64 or complex128, single-kernel lengths (fftc_max_single_n) that
+ * have a compiled kernel (every length of fftc_compiled_entry);
+ * UNSUPPORTED_SIZE otherwise, INVALID_ARG for a bad or self-overlapping
+ * layout.  No device allocation besides the twiddle table.
+ */
+fftc_status fftc_plan_layout(int64_t n, int64_t batch, int direction, int dtype, const fftc_layout *in,
+                             const fftc_layout *out, fftc_plan_t *plan_out);
+
+/*
+ * Execute a layout plan.  Interleaved sides pass the complex array as *_re
+ * and NULL as *_im; planar sides pass both arrays (each aligned to its real
+ * type).  In place is allowed when both layouts are equal and the pointers
+ * are the same; other overlaps are not.  fftc_execute also runs layout plans
+ * whose two sides are interleaved.
+ */
+fftc_status fftc_execute_layout(fftc_plan_t plan, const void *in_re, const void *in_im, void *out_re,
+                                void *out_im, void *stream);
+
 /* Free the plan's device memory.  NULL is a no-op.  The caller must ensure
  * no execution of the plan is still in flight. */
 fftc_status fftc_destroy_plan(fftc_plan_t plan);
@@ -134,6 +175,9 @@ typedef struct {
     int formula_passes, formula_folded, formula_lds;
     int64_t formula_fold_n, formula_fold_p;
     int formula_kernels;
+    /* layout plans: the in and out layouts (interleaved contiguous otherwise) */
+    int has_layout;
+    fftc_layout layout_in, layout_out;
 } fftc_plan_desc;
 
 fftc_status fftc_plan_describe(fftc_plan_t plan, fftc_plan_desc *desc);

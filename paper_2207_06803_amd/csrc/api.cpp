@@ -305,6 +305,11 @@ static fftc_status execute_impl(fftc_plan_t p, const void* in, void* out, int64_
         return launch_mixed(p, in, out, s);
     }
     if (batch < 1 || batch > p->batch) return fail(FFTC_ERR_INVALID_ARG, "batch must be in [1, plan batch]");
+    if (p->has_layout) {
+        if (p->lin.planar || p->lout.planar)
+            return fail(FFTC_ERR_INVALID_ARG, "planar layout plans run through fftc_execute_layout");
+        return launch_layout(p, in, nullptr, out, nullptr, batch, s);
+    }
     if (p->variant == FFTC_VARIANT_FORMULA) {
         if (p->inner) return execute_impl(p->inner, in, out, batch * p->fold_p, stream);
         return formula_launch(p->formula, in, out, batch, p->direction == FFTC_INVERSE, s);
@@ -367,6 +372,11 @@ fftc_status fftc_plan_describe(fftc_plan_t p, fftc_plan_desc* d) {
         d->persistent_groups = p->mixed->groups;
         d->twiddle_bytes = p->mixed->dev_bytes;
     }
+    if (p->has_layout) {
+        d->has_layout = 1;
+        d->layout_in = p->lin;
+        d->layout_out = p->lout;
+    }
     if (p->variant == FFTC_VARIANT_FORMULA) {
         d->formula_passes = p->formula_passes;
         d->formula_folded = p->inner ? 1 : 0;
@@ -384,6 +394,102 @@ fftc_status fftc_plan_describe(fftc_plan_t p, fftc_plan_desc* d) {
         }
     }
     return FFTC_OK;
+}
+
+static fftc_status check_layout(const fftc_layout& l, int64_t n, int64_t batch, const char* side) {
+    const std::string w = std::string(side) + " layout: ";
+    if (l.planar != 0 && l.planar != 1) return fail(FFTC_ERR_INVALID_ARG, w + "planar must be 0 or 1");
+    const int64_t lim = int64_t(1) << 40;
+    if (l.stride < 1 || l.dist < 1 || l.stride > lim || l.dist > lim)
+        return fail(FFTC_ERR_INVALID_ARG, w + "stride and dist must be in [1, 2^40]");
+    const bool blocks = l.dist >= (n - 1) * l.stride + 1;
+    const bool interleaved = l.stride / l.dist >= batch;
+    if (!blocks && !interleaved)
+        return fail(FFTC_ERR_INVALID_ARG, w + "transforms share elements (need dist >= (n-1) stride + 1 or "
+                                              "stride >= batch dist)");
+    return FFTC_OK;
+}
+
+fftc_status fftc_plan_layout(int64_t n, int64_t batch, int direction, int dtype, const fftc_layout* in,
+                             const fftc_layout* out, fftc_plan_t* plan_out) {
+    try {
+        clear_error();
+        if (!plan_out) return fail(FFTC_ERR_INVALID_ARG, "plan_out is NULL");
+        *plan_out = nullptr;
+        if (direction != FFTC_FORWARD && direction != FFTC_INVERSE)
+            return fail(FFTC_ERR_INVALID_ARG, "direction must be FFTC_FORWARD (-1) or FFTC_INVERSE (+1)");
+        if (dtype != FFTC_C64 && dtype != FFTC_C128)
+            return fail(FFTC_ERR_INVALID_ARG, "layout plans take FFTC_C64 or FFTC_C128");
+        if (batch < 1 || batch > (int64_t(1) << 40)) return fail(FFTC_ERR_INVALID_ARG, "batch must be in [1, 2^40]");
+        if (n < 2 || n > max_single_n(dtype) || !is_7smooth(n))
+            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "layout plans take single-kernel lengths 2 <= n <= " +
+                                                       std::to_string(max_single_n(dtype)) + " with prime factors <= 7");
+        const fftc_layout dflt{1, n, 0};
+        const fftc_layout li = in ? *in : dflt, lo = out ? *out : dflt;
+        fftc_status st = check_layout(li, n, batch, "in");
+        if (st == FFTC_OK) st = check_layout(lo, n, batch, "out");
+        if (st != FFTC_OK) return st;
+        std::vector<int> rs = choose_radices(n, dtype);
+        const SpecEntry* e = find_layout(dtype, n, rs);
+        if (!e) {
+            auto c = radix_candidates(n, 1);
+            if (!c.empty() && (e = find_layout(dtype, n, c[0])) != nullptr) rs = c[0];
+        }
+        if (!e)
+            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no compiled layout kernel for n = " + std::to_string(n));
+        fftc_plan_s* p = new (std::nothrow) fftc_plan_s();
+        if (!p) return fail(FFTC_ERR_OUT_OF_MEMORY, "host allocation failed");
+        p->n = n;
+        p->batch = batch;
+        p->direction = direction;
+        p->dtype = dtype;
+        hipGetDevice(&p->device);
+        p->variant = FFTC_VARIANT_SINGLE_SPECIALISED;
+        p->radices = rs;
+        p->spec = e;
+        p->tpt = e->tpt;
+        p->t = e->t;
+        p->has_layout = true;
+        p->lin = li;
+        p->lout = lo;
+        std::vector<TwSegment> segs;
+        const int64_t entries = stage_segments(rs, 0, &segs);
+        st = alloc_tables(p, segs, entries);
+        if (st != FFTC_OK) {
+            std::string keep = t_last_error;
+            fftc_destroy_plan(p);
+            t_last_error = keep;
+            return st;
+        }
+        *plan_out = p;
+        return FFTC_OK;
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_plan_layout");
+    }
+}
+
+fftc_status fftc_execute_layout(fftc_plan_t p, const void* in_re, const void* in_im, void* out_re, void* out_im,
+                                void* stream) {
+    clear_error();
+    if (!p) return fail(FFTC_ERR_INVALID_ARG, "plan is NULL");
+    if (!p->has_layout) return fail(FFTC_ERR_INVALID_ARG, "not a layout plan (fftc_plan_layout)");
+    if (!in_re || !out_re) return fail(FFTC_ERR_INVALID_ARG, "in_re/out_re is NULL");
+    if (p->lin.planar ? !in_im : in_im != nullptr)
+        return fail(FFTC_ERR_INVALID_ARG, p->lin.planar ? "planar input needs in_im" : "interleaved input: in_im must be NULL");
+    if (p->lout.planar ? !out_im : out_im != nullptr)
+        return fail(FFTC_ERR_INVALID_ARG, p->lout.planar ? "planar output needs out_im" : "interleaved output: out_im must be NULL");
+    const uintptr_t real = p->dtype == FFTC_C128 ? 8 : 4;
+    auto aligned = [&](const void* q, bool planar) { return q == nullptr || (uintptr_t)q % (planar ? real : 2 * real) == 0; };
+    if (!aligned(in_re, p->lin.planar) || !aligned(in_im, true) || !aligned(out_re, p->lout.planar) ||
+        !aligned(out_im, true))
+        return fail(FFTC_ERR_INVALID_ARG, "pointer not aligned to its element type");
+    const bool touch = in_re == out_re || (in_im && (in_im == out_re || in_im == out_im)) || (out_im && in_re == out_im);
+    if (touch) {
+        const bool same = in_re == out_re && in_im == out_im && p->lin.planar == p->lout.planar &&
+                          p->lin.stride == p->lout.stride && p->lin.dist == p->lout.dist;
+        if (!same) return fail(FFTC_ERR_INVALID_ARG, "in place needs equal layouts and equal pointers");
+    }
+    return launch_layout(p, in_re, in_im, out_re, out_im, p->batch, static_cast<hipStream_t>(stream));
 }
 
 fftc_status fftc_plan_formula(const char* formula, int64_t batch, int direction, int dtype, int flags,

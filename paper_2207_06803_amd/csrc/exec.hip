@@ -153,6 +153,45 @@ static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* o
     return FFTC_OK;
 }
 
+// Layout plans: the compiled kernel with GAcc accessors.  Interleaved sides
+// count in reals (element step 2 stride, transform step 2 dist, im = re + 1).
+template <typename Real>
+static GAcc<Real> make_acc(const fftc_layout& l, const void* re, const void* im) {
+    GAcc<Real> a;
+    a.re = static_cast<Real*>(const_cast<void*>(re));
+    if (l.planar) {
+        a.im = static_cast<Real*>(const_cast<void*>(im));
+        a.es = l.stride;
+        a.ts = l.dist;
+    } else {
+        a.im = a.re + 1;
+        a.es = 2 * l.stride;
+        a.ts = 2 * l.dist;
+    }
+    return a;
+}
+
+fftc_status launch_layout(const fftc_plan_s* p, const void* in_re, const void* in_im, void* out_re, void* out_im,
+                          int64_t batch, hipStream_t s) {
+    const bool inv = p->direction == FFTC_INVERSE;
+    const int64_t groups = (batch + p->spec->t - 1) / p->spec->t;
+    const void* fn = inv ? p->spec->inv : p->spec->fwd;
+    hipError_t e;
+    if (p->dtype == FFTC_C128) {
+        GAcc<double> a = make_acc<double>(p->lin, in_re, in_im), b = make_acc<double>(p->lout, out_re, out_im);
+        const double2* tw = static_cast<const double2*>(p->tw);
+        void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
+        e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(p->spec->tpt * p->spec->t), args, 0, s);
+    } else {
+        GAcc<float> a = make_acc<float>(p->lin, in_re, in_im), b = make_acc<float>(p->lout, out_re, out_im);
+        const float2* tw = static_cast<const float2*>(p->tw);
+        void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
+        e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(p->spec->tpt * p->spec->t), args, 0, s);
+    }
+    if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(stockham_spec_layout)");
+    return FFTC_OK;
+}
+
 fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s) {
     return p->dtype == FFTC_C128 ? launch_single_t<double>(p, in, out, batch, s)
                                  : launch_single_t<float>(p, in, out, batch, s);

@@ -42,7 +42,8 @@ fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C*
     }
     __syncthreads();
     const int tr = tid / TPT, t = tid - tr * TPT;
-    spec_stages<K, 1, 0, true, false, false, Rs...>(nullptr, nullptr, lds + tr * LDSN, tw, t, true, true);
+    spec_stages<K, 1, 0, true, false, false, Rs...>((const C*)nullptr, (C*)nullptr, lds + tr * LDSN, tw, t, true,
+                                                     true);
     if constexpr (PASS == 1) {
         // row-major store of column i = col0 + c: z[i M + p] w_N^{i p} (i p < N),
         // the factor formed from the fine and coarse tables

@@ -37,12 +37,17 @@ struct fftc_plan_s {
     int64_t fold_n = 0, fold_p = 0;
     int formula_passes = 0, formula_kernels = 0;
     bool formula_lds = false;
+    // layout plan: the compiled kernel with layout accessors, and the layouts
+    bool has_layout = false;
+    fftc_layout lin{}, lout{};
 };
 
 namespace fftc {
 
 // `batch` <= p->batch: run the first `batch` transforms.
 fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);
+fftc_status launch_layout(const fftc_plan_s* p, const void* in_re, const void* in_im, void* out_re, void* out_im,
+                          int64_t batch, hipStream_t s);
 fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);
 fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count);
 fftc_status launch_mixed(fftc_plan_s* p, const void* in, void* out, hipStream_t s);

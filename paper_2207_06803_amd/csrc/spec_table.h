@@ -24,6 +24,12 @@ struct SpecInst {
                     reinterpret_cast<const void*>(&stockham_spec<KI, Rs...>), id};
         return e;
     }
+    static SpecEntry layout_entry(int dtype) {
+        SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
+                    reinterpret_cast<const void*>(&stockham_spec_layout<KF, Rs...>),
+                    reinterpret_cast<const void*>(&stockham_spec_layout<KI, Rs...>), -1};
+        return e;
+    }
 };
 
 // One work item of a compiled list inside the persistent mixed-length kernel:

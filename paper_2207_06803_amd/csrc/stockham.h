@@ -38,6 +38,39 @@ template <bool INV, typename C> __device__ __forceinline__ void st_out(C* p, C v
     __builtin_nontemporal_store(t, reinterpret_cast<V*>(p));
 }
 
+// Any other layout (planar re / im arrays, element strides, gaps between
+// transforms): element e of transform q at re[q ts + e es] and
+// im[q ts + e es] (interleaved complex: im = re + 1 and es, ts counted in
+// reals).  The kernels address a transform through gshift (transform
+// offset) and gld / gst (element e), with a plain complex pointer for the
+// default contiguous layout.
+template <typename Real> struct GAcc {
+    Real* re;
+    Real* im;
+    int64_t es, ts;
+};
+
+template <typename C> __device__ __forceinline__ C* gshift(C* p, int64_t off) { return p + off; }
+template <typename C> __device__ __forceinline__ const C* gshift(const C* p, int64_t off) { return p + off; }
+template <typename Real> __device__ __forceinline__ GAcc<Real> gshift(GAcc<Real> a, int64_t q) {
+    a.re += q * a.ts;
+    a.im += q * a.ts;
+    return a;
+}
+template <bool INV, typename C> __device__ __forceinline__ C gld(const C* p, int e) { return ld_in<INV>(p + e); }
+template <bool INV, typename Real> __device__ __forceinline__ cplx<Real> gld(const GAcc<Real>& a, int e) {
+    const int64_t o = (int64_t)e * a.es;
+    cplx<Real> v = mk(__builtin_nontemporal_load(a.re + o), __builtin_nontemporal_load(a.im + o));
+    return INV ? cconj(v) : v;
+}
+template <bool INV, typename C> __device__ __forceinline__ void gst(C* p, int e, C v) { st_out<INV>(p + e, v); }
+template <bool INV, typename Real> __device__ __forceinline__ void gst(const GAcc<Real>& a, int e, cplx<Real> v) {
+    const int64_t o = (int64_t)e * a.es;
+    if (INV) v = cconj(v);
+    __builtin_nontemporal_store(v.x, a.re + o);
+    __builtin_nontemporal_store(v.y, a.im + o);
+}
+
 // Multiply v[r] (r >= 1) by w_{Ns R}^{r k}, with tq = table + k (entry
 // [(r-1) Ns + k] at tq[(r-1) ns]).  For R = 8 and 16 only the factors
 // r = 1, 2, 3 and r = 4, 8, 12 are read and the rest formed as one product
@@ -85,15 +118,15 @@ __device__ __forceinline__ void apply_twiddles(C* v, const C* __restrict__ tq) {
 // ---------------------------------------------------------------------------
 template <typename Real, int N_, int TPT_, int T_, bool INV_>
 struct SpecCfg {
+    using RealT = Real;
     using C = cplx<Real>;
     static constexpr int N = N_, TPT = TPT_, T = T_;
     static constexpr bool INV = INV_;
     static constexpr bool STAGED = TPT_ < 16;
 };
 
-template <class K, int R, int NS, int TWOFF, bool SRC_G, bool DST_G>
-__device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K::C* gout,
-                                           typename K::C* lds,
+template <class K, int R, int NS, int TWOFF, bool SRC_G, bool DST_G, class GI, class GO>
+__device__ __forceinline__ void spec_stage(GI gin, GO gout, typename K::C* lds,
                                            const typename K::C* __restrict__ tw, int t, bool valid,
                                            bool active) {
     using C = typename K::C;
@@ -111,7 +144,7 @@ __device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K:
                 if constexpr (SRC_G) {
                     // unconditional: the caller points gin at a real transform
                     // for out-of-range slots, whose results are never stored
-                    v[i][r] = ld_in<K::INV>(gin + j + r * NR);
+                    v[i][r] = gld<K::INV>(gin, j + r * NR);
                 } else {
                     v[i][r] = lds[lds_pad(j + r * NR)];
                 }
@@ -130,7 +163,7 @@ __device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K:
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if constexpr (DST_G) {
-                    if (valid) st_out<K::INV>(gout + base + r * NS, v[i][r]);
+                    if (valid) gst<K::INV>(gout, base + r * NS, v[i][r]);
                 } else {
                     lds[lds_pad(base + r * NS)] = v[i][r];
                 }
@@ -140,9 +173,8 @@ __device__ __forceinline__ void spec_stage(const typename K::C* gin, typename K:
     if constexpr (!DST_G) __syncthreads();
 }
 
-template <class K, int NS, int TWOFF, bool FIRST, bool SG, bool DG, int R, int... Rest>
-__device__ __forceinline__ void spec_stages(const typename K::C* gin, typename K::C* gout,
-                                            typename K::C* lds,
+template <class K, int NS, int TWOFF, bool FIRST, bool SG, bool DG, int R, int... Rest, class GI, class GO>
+__device__ __forceinline__ void spec_stages(GI gin, GO gout, typename K::C* lds,
                                             const typename K::C* __restrict__ tw, int t, bool valid,
                                             bool active) {
     constexpr bool LAST = sizeof...(Rest) == 0;
@@ -158,9 +190,9 @@ template <class K, int NR> struct SpecLds {
 
 // The transforms of one group: transform q < count starts at element toff(q)
 // of in and out.  All NTH threads of the workgroup call this (NTH >= TPT T).
-template <class K, int NTH, class OffF, int... Rs>
-__device__ __forceinline__ void spec_group(const typename K::C* in, typename K::C* out, OffF toff, int count,
-                                           typename K::C* lds, const typename K::C* __restrict__ tw, int tid) {
+template <class K, int NTH, class OffF, int... Rs, class GI, class GO>
+__device__ __forceinline__ void spec_group(GI in, GO out, OffF toff, int count, typename K::C* lds,
+                                           const typename K::C* __restrict__ tw, int tid) {
     using C = typename K::C;
     constexpr int N = K::N, TPT = K::TPT, T = K::T;
     constexpr int LDSN = SpecLds<K, sizeof...(Rs)>::LDSN;
@@ -177,7 +209,7 @@ __device__ __forceinline__ void spec_group(const typename K::C* in, typename K::
         for (int i = 0; i < ITER; ++i) {
             const int l = tid + i * NTH;
             const int q = min(l / N, count - 1);  // clamp: always a real transform
-            buf[i] = ld_in<K::INV>(in + toff(q) + (l % N));
+            buf[i] = gld<K::INV>(gshift(in, toff(q)), l % N);
         }
 #pragma unroll
         for (int i = 0; i < ITER; ++i) {
@@ -185,16 +217,18 @@ __device__ __forceinline__ void spec_group(const typename K::C* in, typename K::
             if (l < TOT) lds[(l / N) * LDSN + lds_pad(l % N)] = buf[i];
         }
         __syncthreads();
-        spec_stages<K, 1, 0, true, false, false, Rs...>(nullptr, nullptr, mylds, tw, t, valid, member);
+        spec_stages<K, 1, 0, true, false, false, Rs...>((const C*)nullptr, (C*)nullptr, mylds, tw, t, valid,
+                                                         member);
 #pragma unroll
         for (int i = 0; i < ITER; ++i) {
             const int l = tid + i * NTH;
             const int q = l / N;
-            if (l < TOT && q < count) st_out<K::INV>(out + toff(q) + (l % N), lds[q * LDSN + lds_pad(l % N)]);
+            if (l < TOT && q < count) gst<K::INV>(gshift(out, toff(q)), l % N, lds[q * LDSN + lds_pad(l % N)]);
         }
     } else {
         const int64_t off = toff(valid ? tr : 0);
-        spec_stages<K, 1, 0, true, true, true, Rs...>(in + off, out + off, mylds, tw, t, valid, member);
+        spec_stages<K, 1, 0, true, true, true, Rs...>(gshift(in, off), gshift(out, off), mylds, tw, t, valid,
+                                                       member);
     }
 }
 
@@ -213,6 +247,25 @@ stockham_spec(const typename K::C* in, typename K::C* out,
     const int64_t b0 = (int64_t)blockIdx.x * T;
     const int count = (int)min((int64_t)T, batch - b0);
     spec_group<K, NTH, ContigOff, Rs...>(in, out, ContigOff{b0 * N, N}, count, lds, tw, (int)threadIdx.x);
+}
+
+// The same transform for any other layout (GAcc): transform q of the
+// launch is transform b0 + q of the layout.
+struct IndexOff {
+    int64_t base;
+    __device__ __forceinline__ int64_t operator()(int q) const { return base + q; }
+};
+
+template <class K, int... Rs>
+__global__ void __launch_bounds__(K::TPT * K::T)
+stockham_spec_layout(GAcc<typename K::RealT> in, GAcc<typename K::RealT> out,
+                     const typename K::C* __restrict__ tw, int64_t batch) {
+    using C = typename K::C;
+    constexpr int T = K::T, NTH = K::TPT * K::T;
+    __shared__ C lds[T * SpecLds<K, sizeof...(Rs)>::LDSN];
+    const int64_t b0 = (int64_t)blockIdx.x * T;
+    const int count = (int)min((int64_t)T, batch - b0);
+    spec_group<K, NTH, IndexOff, Rs...>(in, out, IndexOff{b0}, count, lds, tw, (int)threadIdx.x);
 }
 
 }  // namespace fftc

@@ -47,6 +47,10 @@ class FFTCError(RuntimeError):
         super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
 
 
+class Layout(ctypes.Structure):
+    _fields_ = [("stride", ctypes.c_int64), ("dist", ctypes.c_int64), ("planar", ctypes.c_int)]
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("batch", ctypes.c_int64), ("direction", ctypes.c_int),
                 ("dtype", ctypes.c_int), ("variant", ctypes.c_int), ("nradices", ctypes.c_int),
@@ -58,7 +62,8 @@ class PlanDesc(ctypes.Structure):
                 ("mixed_items", ctypes.c_int), ("persistent_groups", ctypes.c_int),
                 ("formula_passes", ctypes.c_int), ("formula_folded", ctypes.c_int),
                 ("formula_lds", ctypes.c_int), ("formula_fold_n", ctypes.c_int64),
-                ("formula_fold_p", ctypes.c_int64), ("formula_kernels", ctypes.c_int)]
+                ("formula_fold_p", ctypes.c_int64), ("formula_kernels", ctypes.c_int),
+                ("has_layout", ctypes.c_int), ("layout_in", Layout), ("layout_out", Layout)]
 
 
 _i64, _int, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
@@ -86,6 +91,9 @@ _SIGNATURES = {
     "fftc_formula_lower": (_int, [ctypes.c_char_p, _int, _int, ctypes.POINTER(_i64), ctypes.c_char_p,
                                   ctypes.c_size_t]),
     "fftc_formula_max_lds_dim": (_i64, [_int]),
+    "fftc_plan_layout": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(Layout), ctypes.POINTER(Layout),
+                                ctypes.POINTER(_vp)]),
+    "fftc_execute_layout": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "fftc_status_string": (ctypes.c_char_p, [_int]),
     "fftc_last_error": (ctypes.c_char_p, []),
 }
@@ -225,7 +233,10 @@ class Plan:
                 "persistent_groups": d.persistent_groups,
                 "formula_passes": d.formula_passes, "formula_folded": bool(d.formula_folded),
                 "formula_lds": bool(d.formula_lds), "formula_fold_n": d.formula_fold_n,
-                "formula_fold_p": d.formula_fold_p, "formula_kernels": d.formula_kernels}
+                "formula_fold_p": d.formula_fold_p, "formula_kernels": d.formula_kernels,
+                "has_layout": bool(d.has_layout),
+                "layout_in": (d.layout_in.stride, d.layout_in.dist, d.layout_in.planar),
+                "layout_out": (d.layout_out.stride, d.layout_out.dist, d.layout_out.planar)}
 
     def close(self) -> None:
         if self._h is not None and self._h.value:
@@ -284,6 +295,23 @@ def formula_lower(formula: str, flags: int = 0, dtype="c64"):
 
 def formula_max_lds_dim(dtype="c64") -> int:
     return int(lib.fftc_formula_max_lds_dim(dtype_code(dtype)))
+
+
+def plan_layout(n: int, batch: int, direction: int = FORWARD, dtype="c64", in_layout=None, out_layout=None) -> Plan:
+    """Plan reading and writing planar and/or strided data.  A layout is
+    (stride, dist, planar) in elements; None = interleaved contiguous."""
+    def mk(l):
+        return None if l is None else ctypes.byref(Layout(int(l[0]), int(l[1]), int(l[2])))
+    h = _vp()
+    check(lib.fftc_plan_layout(n, batch, direction, dtype_code(dtype), mk(in_layout), mk(out_layout),
+                               ctypes.byref(h)), "fftc_plan_layout")
+    return Plan(n, batch, direction, dtype, _handle=h)
+
+
+def execute_layout(plan: Plan, in_re, in_im, out_re, out_im, stream=None) -> None:
+    """Run a layout plan: planar sides give (re, im), interleaved sides (array, None)."""
+    check(lib.fftc_execute_layout(plan._h, ptr(in_re), ptr(in_im) or None, ptr(out_re), ptr(out_im) or None,
+                                  stream_handle(stream)), "fftc_execute_layout")
 
 
 def autotune(n: int, batch: int, dtype="c64", reps: int = 10):
