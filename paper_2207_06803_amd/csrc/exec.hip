@@ -174,19 +174,28 @@ static GAcc<Real> make_acc(const fftc_layout& l, const void* re, const void* im)
 fftc_status launch_layout(const fftc_plan_s* p, const void* in_re, const void* in_im, void* out_re, void* out_im,
                           int64_t batch, hipStream_t s) {
     const bool inv = p->direction == FFTC_INVERSE;
-    const int64_t groups = (batch + p->spec->t - 1) / p->spec->t;
-    const void* fn = inv ? p->spec->inv : p->spec->fwd;
+    // column-like sides (dist < stride) go through the tile kernel
+    int in_cols = p->lin.dist < p->lin.stride ? 1 : 0, out_cols = p->lout.dist < p->lout.stride ? 1 : 0;
+    const bool tile = (in_cols || out_cols) && p->spec->tile_fwd;
+    const int per = tile ? p->spec->tile_tc : p->spec->t;
+    const int threads = tile ? p->spec->tile_tpt * p->spec->tile_tc : p->spec->tpt * p->spec->t;
+    const int64_t groups = (batch + per - 1) / per;
+    const void* fn = tile ? (inv ? p->spec->tile_inv : p->spec->tile_fwd) : (inv ? p->spec->inv : p->spec->fwd);
     hipError_t e;
     if (p->dtype == FFTC_C128) {
         GAcc<double> a = make_acc<double>(p->lin, in_re, in_im), b = make_acc<double>(p->lout, out_re, out_im);
         const double2* tw = static_cast<const double2*>(p->tw);
-        void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
-        e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(p->spec->tpt * p->spec->t), args, 0, s);
+        // the tile kernel takes the two order flags as well
+        void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch, (void*)&in_cols, (void*)&out_cols};
+        void* args4[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
+        e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), tile ? args : args4, 0, s);
     } else {
         GAcc<float> a = make_acc<float>(p->lin, in_re, in_im), b = make_acc<float>(p->lout, out_re, out_im);
         const float2* tw = static_cast<const float2*>(p->tw);
-        void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
-        e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(p->spec->tpt * p->spec->t), args, 0, s);
+        // the tile kernel takes the two order flags as well
+        void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch, (void*)&in_cols, (void*)&out_cols};
+        void* args4[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
+        e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), tile ? args : args4, 0, s);
     }
     if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(stockham_spec_layout)");
     return FFTC_OK;

@@ -49,6 +49,10 @@ struct SpecEntry {
     const void* fwd;
     const void* inv;
     int id;  // index in the dtype's compiled list (body id in mixed kernels)
+    // layout entries: the tile kernel for column-like layouts
+    const void* tile_fwd = nullptr;
+    const void* tile_inv = nullptr;
+    int tile_tpt = 0, tile_tc = 0;
 };
 // Compiled specialisations, in kSpecParts translation units per dtype.
 constexpr int kSpecParts = 4;

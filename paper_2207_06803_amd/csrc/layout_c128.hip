@@ -1,11 +1,12 @@
 // c128 Stockham kernels with the layout accessors (planar and strided data):
-// the preferred radix list of every compiled length.
+// the preferred radix list of every compiled length, each with its tile
+// kernel for column-like layouts.
 #include "spec_list.inc"
-#include "spec_table.h"
+#include "layout_tile.h"
 
 namespace fftc {
 
-#define E(N, ...) SpecInst<double, N, __VA_ARGS__>::layout_entry(FFTC_C128),
+#define E(N, ...) layout_entry_with_tile<double, N, __VA_ARGS__>(FFTC_C128),
 static const SpecEntry k_table[] = {FFTC_LAYOUT_LIST_C128(E)};
 #undef E
 

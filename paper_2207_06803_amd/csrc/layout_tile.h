@@ -1,0 +1,83 @@
+// Layout plans whose transforms are interleaved element by element (a
+// layout with dist < stride: the columns of a row-major array).  Loading
+// one transform per lane group would touch one element per row; instead a
+// workgroup owns TC consecutive transforms and moves the tile between HBM
+// and LDS in the order the layout makes contiguous -- consecutive lanes on
+// consecutive transforms for a column-like side, on consecutive elements
+// otherwise -- then runs the compiled Stockham stages LDS to LDS (the
+// column kernels of the two-pass plans, with the layout accessors).
+#pragma once
+#include "spec_table.h"
+
+namespace fftc {
+
+template <class K, bool INV, int... Rs>
+__global__ void __launch_bounds__(K::TPT * K::T)
+stockham_tile_layout(GAcc<typename K::RealT> in, GAcc<typename K::RealT> out,
+                     const typename K::C* __restrict__ tw, int64_t batch, int in_cols, int out_cols) {
+    using C = typename K::C;
+    constexpr int LEN = K::N, TPT = K::TPT, TC = K::T, NTH = TPT * TC;
+    constexpr int LDSN = lds_len(LEN);
+    constexpr int TOT = TC * LEN, IT = (TOT + NTH - 1) / NTH;
+    __shared__ C lds[TC * LDSN];
+    const int tid = (int)threadIdx.x;
+    const int64_t col0 = (int64_t)blockIdx.x * TC;
+    const int cols = (int)min((int64_t)TC, batch - col0);
+    C buf[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int l = tid + i * NTH;
+        const int c = in_cols ? l % TC : l / LEN, j = in_cols ? l / TC : l % LEN;
+        // clamped: every load reads a real element of a real transform
+        const int cc = (c < cols) ? c : 0, jj = min(j, LEN - 1);
+        buf[i] = gld<INV>(gshift(in, col0 + cc), jj);
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int l = tid + i * NTH;
+        const int c = in_cols ? l % TC : l / LEN, j = in_cols ? l / TC : l % LEN;
+        if (l < TOT) lds[c * LDSN + lds_pad(j)] = buf[i];
+    }
+    __syncthreads();
+    const int tr = tid / TPT, t = tid - tr * TPT;
+    spec_stages<K, 1, 0, true, false, false, Rs...>((const C*)nullptr, (C*)nullptr, lds + tr * LDSN, tw, t, true,
+                                                     true);
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int l = tid + i * NTH;
+        const int c = out_cols ? l % TC : l / LEN, j = out_cols ? l / TC : l % LEN;
+        if (l < TOT && c < cols) gst<INV>(gshift(out, col0 + c), j, lds[c * LDSN + lds_pad(j)]);
+    }
+}
+
+// Transforms per tile: 128 contiguous bytes per row where LDS allows.
+constexpr int tile_cols(int n, int csize) {
+    int tc = 128 / csize;
+    while (tc > 1 && tc * lds_len(n) * csize > kLdsMaxPerGroup) tc /= 2;
+    return tc;
+}
+
+template <typename Real, int N, int... Rs>
+struct TileInst {
+    static constexpr int rs[sizeof...(Rs)] = {Rs...};
+    static constexpr int TC0 = tile_cols(N, (int)sizeof(cplx<Real>));
+    static constexpr int TPT = round_tpt(required_tpt(N, rs, (int)sizeof...(Rs)));
+    static constexpr int TC = (TPT * TC0 > 1024) ? 1024 / TPT : TC0;
+    static_assert(TC >= 1 && TPT * TC <= 1024, "tile too large");
+    using K = SpecCfg<Real, N, TPT, TC, false>;
+    static void fill(SpecEntry* e) {
+        e->tile_fwd = reinterpret_cast<const void*>(&stockham_tile_layout<K, false, Rs...>);
+        e->tile_inv = reinterpret_cast<const void*>(&stockham_tile_layout<K, true, Rs...>);
+        e->tile_tpt = TPT;
+        e->tile_tc = TC;
+    }
+};
+
+template <typename Real, int N, int... Rs>
+SpecEntry layout_entry_with_tile(int dtype) {
+    SpecEntry e = SpecInst<Real, N, Rs...>::layout_entry(dtype);
+    TileInst<Real, N, Rs...>::fill(&e);
+    return e;
+}
+
+}  // namespace fftc

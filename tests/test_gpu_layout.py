@@ -88,6 +88,7 @@ def layout_lengths(dtype):
 def test_planar_every_length(dtype):
     for n in layout_lengths(dtype):
         b = 3
+        say(f"planar n={n} {dtype}")
         x = synth.uniform_complex(synth.rng(130, n), (b, n), np_dtype(dtype))
         lay = (1, n, 1)
         for d in (FWD, INV):
@@ -99,9 +100,11 @@ def test_planar_every_length(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("n", [8, 12, 64, 256, 1024, 4096, 7 * 512])
+@pytest.mark.parametrize("n", [2, 8, 12, 64, 256, 1024, 4096, 7 * 512, 16384])
 def test_layout_kinds(n, dtype):
-    b = 5
+    if n > fftc.max_single_n(dtype):
+        pytest.skip("beyond the single-kernel lengths of this dtype")
+    b = 5 if n <= 4096 else 3
     x = synth.uniform_complex(synth.rng(131, n), (b, n), np_dtype(dtype))
     cases = [
         ((1, n, 1), (1, n, 0)),                    # planar in, interleaved out (createComplex)
@@ -109,6 +112,8 @@ def test_layout_kinds(n, dtype):
         ((2, 2 * n + 3, 0), (3, 3 * n + 1, 1)),    # strided with gaps
         ((b, 1, 0), (b + 2, 1, 0)),                # columns of a row-major array
         ((b, 1, 1), (1, n + 5, 1)),                # planar columns in, padded planar rows out
+        ((1, n, 0), (b + 1, 1, 1)),                # rows in, planar columns out
+        ((2 * b, 2, 0), (2 * b + 1, 2, 0)),        # every other column
     ]
     for lin, lout in cases:
         for d in (FWD, INV):
@@ -138,6 +143,20 @@ def test_agrees_with_interleaved_plan_and_is_deterministic(dtype):
             y2, _ = run_layout(p, x, (1, n, 1), (1, n, 1), dtype)
         assert np.array_equal(y, y2), n
         assert rel_l2(y, want).max() <= tol_for(n, dtype) / 4, n
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_columns_every_length(dtype):
+    # the tile kernel of every compiled length, with a ragged last tile
+    for n in layout_lengths(dtype):
+        b = 37
+        x = synth.uniform_complex(synth.rng(135, n), (b, n), np_dtype(dtype))
+        lay = (b + 3, 1, 0)
+        say(f"columns n={n} {dtype}")
+        with fftc.plan_layout(n, b, INV, dtype, lay, lay) as p:
+            y, clean = run_layout(p, x, lay, lay, dtype)
+        assert rel_l2(y, oracle.dft(x, INV)).max() <= tol_for(n, dtype), n
+        assert clean
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
