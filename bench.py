@@ -18,6 +18,8 @@ HIP events on the stream its kernels run on):
   * serving: 20,000 Poisson-arriving requests, p50/p99 latency
   * formula plans (the Kronecker-product DSL): Eq. 2 programs folded onto
     the Stockham plans vs run as written, and 2-D DFT formulas
+  * planar and strided layouts: planar in/out, planar in -> interleaved out,
+    and columns of a row-major array, against the interleaved plan
 and the FP64 oracle timed on the host cores as the CPU baseline.
 
 Prints one JSON line.  `value` is GFLOP/s in the 5 N log2 N convention.
@@ -349,6 +351,40 @@ def formula(torch, fftc, synth, timer):
                         "write of every element", "cases": out}
 
 
+def layouts(torch, fftc, synth, timer):
+    """Layout plans at 2^24 complex64 elements per launch."""
+    E = ELEMS
+    g = synth.rng(7)
+    host = synth.uniform_complex(g, (E,), np.complex64)
+    re = [torch.from_numpy(np.ascontiguousarray(host.real)).to("cuda") for _ in range(2)]
+    im = [torch.from_numpy(np.ascontiguousarray(host.imag)).to("cuda") for _ in range(2)]
+    ore, oim = [torch.empty_like(re[0]) for _ in range(2)], [torch.empty_like(re[0]) for _ in range(2)]
+    cx = [torch.from_numpy(host).to("cuda") for _ in range(2)]
+    cy = [torch.empty_like(cx[0]) for _ in range(2)]
+    out = {}
+    for n in (256, 1024, 4096):
+        b = E // n
+        row = {}
+        with fftc.Plan(n, b, fftc.FORWARD, "c64") as p:
+            row["interleaved_us"] = timer.avg_ms(lambda i: p.execute(cx[i % 2], cy[i % 2], timer.s), 10) * 1e3
+        with fftc.plan_layout(n, b, fftc.FORWARD, "c64", (1, n, 1), (1, n, 1)) as p:
+            row["planar_us"] = timer.avg_ms(
+                lambda i: fftc.execute_layout(p, re[i % 2], im[i % 2], ore[i % 2], oim[i % 2], timer.s), 10) * 1e3
+        with fftc.plan_layout(n, b, fftc.FORWARD, "c64", (1, n, 1), None) as p:
+            row["planar_to_interleaved_us"] = timer.avg_ms(
+                lambda i: fftc.execute_layout(p, re[i % 2], im[i % 2], cy[i % 2], None, timer.s), 10) * 1e3
+        with fftc.plan_layout(n, b, fftc.FORWARD, "c64", (b, 1, 0), (b, 1, 0)) as p:
+            row["columns_us"] = timer.avg_ms(
+                lambda i: fftc.execute_layout(p, cx[i % 2], None, cy[i % 2], None, timer.s), 5) * 1e3
+        for k in list(row):
+            row[k.replace("_us", "_gbs")] = 16.0 * E / (row[k] * 1e-6) / 1e9
+        out[str(n)] = row
+    del re, im, ore, oim, cx, cy
+    torch.cuda.empty_cache()
+    return {"workload": "complex64 forward, 2^24 elements per launch; columns = the n x (2^24/n) row-major "
+                        "array transformed along its first axis (stride 2^24/n, dist 1)", "by_n": out}
+
+
 def config5(args, torch, fftc, synth):
     from paper_2207_06803_amd import server as srv
     g = synth.rng(5)
@@ -550,6 +586,7 @@ def main():
                          ("config3_mixed", lambda: config3(torch, fftc, synth, timer)),
                          ("config4_split_precision", lambda: config4(torch, fftc, synth, timer)),
                          ("formula", lambda: formula(torch, fftc, synth, timer)),
+                         ("layouts", lambda: layouts(torch, fftc, synth, timer)),
                          ("config5_serving", lambda: config5(args, torch, fftc, synth))):
             log(f"{name} ...")
             extras[name] = fn()
