@@ -69,7 +69,8 @@ enum {
     FFTC_VARIANT_TWO_PASS = 2,           /* Eq. 2 four-step in two kernels + scratch */
     FFTC_VARIANT_MIXED_PERSISTENT = 3,   /* mixed lengths, one persistent launch in a hipGraph */
     FFTC_VARIANT_SPLIT_MFMA = 4,         /* DFT_16 stages on the matrix cores (split precision) */
-    FFTC_VARIANT_FORMULA = 5             /* a Kronecker-product formula (fftc_plan_formula) */
+    FFTC_VARIANT_FORMULA = 5,            /* a Kronecker-product formula (fftc_plan_formula) */
+    FFTC_VARIANT_ORDER = 6               /* an alternative factorisation order (fftc_plan_order) */
 };
 
 typedef struct fftc_plan_s *fftc_plan_t;
@@ -178,6 +179,8 @@ typedef struct {
     /* layout plans: the in and out layouts (interleaved contiguous otherwise) */
     int has_layout;
     fftc_layout layout_in, layout_out;
+    /* order plans: FFTC_ORDER_* and the radix */
+    int order, order_radix;
 } fftc_plan_desc;
 
 fftc_status fftc_plan_describe(fftc_plan_t plan, fftc_plan_desc *desc);
@@ -287,6 +290,40 @@ fftc_status fftc_plan_mixed(const int64_t *n, int64_t count, int direction, int 
  */
 fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int *radices,
                           int max_count, int *count, double *best_us);
+
+/* ---------------------------------------------------------------------------
+ * Alternative factorisation orders (Sections I-II: the factorisation that
+ * suits the hardware is an open choice -- Stockham, Pease, or the recursive
+ * Cooley-Tukey form the paper runs).  For N = radix^t (N = 64, 256, 1024,
+ * 4096 with the radices listed by fftc_order_entry), one LDS-resident kernel
+ * per order:
+ *   FFTC_ORDER_CT     Eq. 2 unrolled: explicit digit reversal of the input
+ *                     (the product of the recursion's Pi factors), then t
+ *                     in-place radix-R stages (decimation in time);
+ *   FFTC_ORDER_PEASE  constant geometry: every stage reads x[j + r N/R] and
+ *                     writes y[j R + r]; explicit digit reversal on output.
+ * Same conventions and results as fftc_plan (up to rounding).
+ * ------------------------------------------------------------------------- */
+enum { FFTC_ORDER_STOCKHAM = 0, FFTC_ORDER_CT = 1, FFTC_ORDER_PEASE = 2 };
+
+fftc_status fftc_plan_order(int64_t n, int64_t batch, int direction, int dtype, int order, int radix,
+                            fftc_plan_t *plan_out);
+
+/* Host-only: the compiled (n, order, radix) triples for dtype. */
+int fftc_order_count(int dtype);
+fftc_status fftc_order_entry(int dtype, int i, int64_t *n, int *order, int *radix);
+
+/*
+ * Order autotuner: times the Stockham plan (its tuned or preferred list) and
+ * every compiled (order, radix) for n, like fftc_autotune (best of three
+ * trials of `reps` launches, forward, internal buffers).  Writes up to `max`
+ * results (orders[i], radices[i] -- 0 for Stockham -- and us[i]), the count,
+ * and the index of the fastest; a non-Stockham order wins only by more than
+ * 1%.  The winner is recorded in the tuning database, and fftc_plan then
+ * uses that order for (n, dtype).
+ */
+fftc_status fftc_autotune_orders(int64_t n, int64_t batch, int dtype, int reps, int *orders, int *radices,
+                                 double *us, int max, int *count, int *best);
 
 /* Tuning database persistence (text, one line per (arch, dtype, n)).  The
  * database is also read once from the file named by FFTC_TUNE_DB, if set.

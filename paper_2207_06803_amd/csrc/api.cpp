@@ -87,6 +87,39 @@ static fftc_status alloc_tables(fftc_plan_s* p, const std::vector<TwSegment>& se
     return make_twiddles(p->tw, p->dtype, segs, nullptr);
 }
 
+// An order plan (orders.h) for a compiled (n, order, radix); the caller has
+// validated direction, dtype and batch.
+static fftc_status plan_order_impl(int64_t n, int64_t batch, int direction, int dtype, const OrderEntry* o,
+                                   fftc_plan_t* out) {
+    fftc_plan_s* p = new (std::nothrow) fftc_plan_s();
+    if (!p) return fail(FFTC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->n = n;
+    p->batch = batch;
+    p->direction = direction;
+    p->dtype = dtype;
+    hipGetDevice(&p->device);
+    p->variant = FFTC_VARIANT_ORDER;
+    p->order = o;
+    p->tpt = o->tpt;
+    p->t = o->t;
+    for (int64_t m = n; m > 1; m /= o->radix) p->radices.push_back(o->radix);
+    // one table of w_N^e, e < N
+    TwSegment seg;
+    seg.off = 0;
+    seg.count = n;
+    seg.ns = n;
+    seg.len = n;
+    fftc_status st = alloc_tables(p, {seg}, n);
+    if (st != FFTC_OK) {
+        std::string keep = t_last_error;
+        fftc_destroy_plan(p);
+        t_last_error = keep;
+        return st;
+    }
+    *out = p;
+    return FFTC_OK;
+}
+
 static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype, const int* radices,
                              int count, fftc_plan_t* out) {
     clear_error();
@@ -114,6 +147,13 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
             return fail(FFTC_ERR_INVALID_ARG, "bad radix count");
         fftc_status cr = check_radices(n, std::vector<int>(radices, radices + count));
         if (cr != FFTC_OK) return cr;
+    }
+    if (!radices && !is_split_dtype(dtype)) {  // an alternative order the order autotuner recorded
+        int order = 0, radix = 0;
+        const OrderEntry* o = nullptr;
+        if (tune_lookup_order(n, dtype, &order, &radix) && (o = find_order(dtype, n, order, radix)) != nullptr &&
+            batch <= (int64_t(1) << 31))
+            return plan_order_impl(n, batch, direction, dtype, o, out);
     }
     fftc_status st = enable_large_lds();
     if (st != FFTC_OK) return st;
@@ -305,6 +345,7 @@ static fftc_status execute_impl(fftc_plan_t p, const void* in, void* out, int64_
         return launch_mixed(p, in, out, s);
     }
     if (batch < 1 || batch > p->batch) return fail(FFTC_ERR_INVALID_ARG, "batch must be in [1, plan batch]");
+    if (p->variant == FFTC_VARIANT_ORDER) return launch_order(p, in, out, batch, s);
     if (p->has_layout) {
         if (p->lin.planar || p->lout.planar)
             return fail(FFTC_ERR_INVALID_ARG, "planar layout plans run through fftc_execute_layout");
@@ -372,6 +413,10 @@ fftc_status fftc_plan_describe(fftc_plan_t p, fftc_plan_desc* d) {
         d->persistent_groups = p->mixed->groups;
         d->twiddle_bytes = p->mixed->dev_bytes;
     }
+    if (p->order) {
+        d->order = p->order->order;
+        d->order_radix = p->order->radix;
+    }
     if (p->has_layout) {
         d->has_layout = 1;
         d->layout_in = p->lin;
@@ -393,6 +438,49 @@ fftc_status fftc_plan_describe(fftc_plan_t p, fftc_plan_desc* d) {
             d->scratch_bytes = p->inner->scratch_bytes;
         }
     }
+    return FFTC_OK;
+}
+
+fftc_status fftc_plan_order(int64_t n, int64_t batch, int direction, int dtype, int order, int radix,
+                            fftc_plan_t* plan_out) {
+    try {
+        clear_error();
+        if (!plan_out) return fail(FFTC_ERR_INVALID_ARG, "plan_out is NULL");
+        *plan_out = nullptr;
+        if (direction != FFTC_FORWARD && direction != FFTC_INVERSE)
+            return fail(FFTC_ERR_INVALID_ARG, "direction must be FFTC_FORWARD (-1) or FFTC_INVERSE (+1)");
+        if (dtype != FFTC_C64 && dtype != FFTC_C128)
+            return fail(FFTC_ERR_INVALID_ARG, "order plans take FFTC_C64 or FFTC_C128");
+        if (batch < 1 || batch > (int64_t(1) << 31)) return fail(FFTC_ERR_INVALID_ARG, "batch must be in [1, 2^31]");
+        if (order != FFTC_ORDER_CT && order != FFTC_ORDER_PEASE)
+            return fail(FFTC_ERR_INVALID_ARG, "order must be FFTC_ORDER_CT or FFTC_ORDER_PEASE");
+        const OrderEntry* o = find_order(dtype, n, order, radix);
+        if (!o)
+            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no compiled kernel for n = " + std::to_string(n) + ", radix " +
+                                                       std::to_string(radix) + " in this order");
+        return plan_order_impl(n, batch, direction, dtype, o, plan_out);
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_plan_order");
+    }
+}
+
+int fftc_order_count(int dtype) {
+    int cnt = 0;
+    if (dtype != FFTC_C64 && dtype != FFTC_C128) return 0;
+    order_table(dtype, &cnt);
+    return cnt;
+}
+
+fftc_status fftc_order_entry(int dtype, int i, int64_t* n, int* order, int* radix) {
+    clear_error();
+    if (!n || !order || !radix) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
+    if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
+    int cnt = 0;
+    const OrderEntry* tab = order_table(dtype, &cnt);
+    if (i < 0 || i >= cnt) return fail(FFTC_ERR_INVALID_ARG, "index out of range");
+    *n = tab[i].n;
+    *order = tab[i].order;
+    *radix = tab[i].radix;
     return FFTC_OK;
 }
 

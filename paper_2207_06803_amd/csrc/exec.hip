@@ -153,6 +153,17 @@ static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* o
     return FFTC_OK;
 }
 
+fftc_status launch_order(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s) {
+    const OrderEntry* o = p->order;
+    const int64_t groups = (batch + o->t - 1) / o->t;
+    const void* tw = p->tw;
+    void* args[] = {(void*)&in, (void*)&out, (void*)&tw, (void*)&batch};
+    hipError_t e = hipLaunchKernel(p->direction == FFTC_INVERSE ? o->inv : o->fwd, dim3((unsigned)groups),
+                                   dim3(o->tpt * o->t), args, 0, s);
+    if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(order_kernel)");
+    return FFTC_OK;
+}
+
 // Layout plans: the compiled kernel with GAcc accessors.  Interleaved sides
 // count in reals (element step 2 stride, transform step 2 dist, im = re + 1).
 template <typename Real>

@@ -37,6 +37,9 @@ std::vector<int> choose_radices(int64_t n, int dtype);
 // Tuning database: best radix list for (n, dtype), if recorded.
 bool tune_lookup(int64_t n, int dtype, std::vector<int>* rs);
 void tune_record(int64_t n, int dtype, const std::vector<int>& rs, double ms);
+// Alternative order recorded for (n, dtype) (FFTC_ORDER_CT / _PEASE), if any.
+bool tune_lookup_order(int64_t n, int dtype, int* order, int* radix);
+void tune_record_order(int64_t n, int dtype, int order, int radix, double ms);
 int tune_load_file(const char* path);
 int tune_save_file(const char* path);
 void tune_clear_all();
@@ -71,6 +74,16 @@ struct FourStepEntry {
     const void* fn[2][2];  // [pass - 1][inverse]
 };
 const FourStepEntry* find_fourstep(int dtype, int64_t len, const std::vector<int>& rs);
+
+// Alternative orders (orders.h): N = radix^t in one LDS-resident kernel.
+struct OrderEntry {
+    int dtype, n, order, radix;
+    int tpt, t;
+    const void* fwd;
+    const void* inv;
+};
+const OrderEntry* order_table(int dtype, int* count);
+const OrderEntry* find_order(int dtype, int64_t n, int order, int radix);
 
 struct TwSegment {
     int64_t off;      // first entry in the table

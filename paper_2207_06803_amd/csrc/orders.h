@@ -1,0 +1,158 @@
+// Alternative factorisation orders, for the autotuner to time against the
+// Stockham kernels.  The paper writes Cooley-Tukey as Eq. 2 applied
+// recursively and runs the recursive (decimation-in-time) form with its
+// stride permutations made explicit; it names the Stockham and Pease orders
+// as alternatives whose merit depends on the hardware.  For N = R^t, one
+// workgroup per T transforms, everything in LDS:
+//
+//  ORDER_CT (Eq. 2 unrolled, decimation in time): the product of the
+//    Pi^N_K factors of the recursion is the base-R digit reversal of the
+//    input index, applied explicitly (the input is written to LDS at the
+//    reversed position); then t in-place stages, stage s with m = R^s,
+//    L = m R: for every butterfly (g, k), k < m, on the elements
+//    g L + k + r m (r < R): v_r *= w_L^{r k}, v = DFT_R v, written back in
+//    place.
+//  ORDER_PEASE (constant geometry): every stage q (ns = R^q) reads
+//    v_r = x[j + r N/R] w_{ns R}^{r rev_q(j mod ns)}, applies DFT_R and writes
+//    y[j R + r] -- the same addresses in every stage (the perfect shuffle) --
+//    with rev_q the reversal of the q low base-R digits; the result is in
+//    digit-reversed order, and the explicit reversal is the store's read
+//    address.  (Derived from the Stockham stages by conjugating each with the
+//    digit permutation that makes its addressing constant.)
+//
+// Twiddles come from one table of w_N^e, e < N (w_L^a = w_N^{a N / L}).
+#pragma once
+#include "codelets.h"
+#include "kconfig.h"
+#include "stockham.h"
+
+namespace fftc {
+
+enum { ORDER_STOCKHAM = 0, ORDER_CT = 1, ORDER_PEASE = 2 };
+
+constexpr int ilog(int n, int r) { return n <= 1 ? 0 : 1 + ilog(n / r, r); }
+
+// reversal of the D low base-R digits of e
+template <int R, int D> __device__ __forceinline__ int drev(int e) {
+    int o = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        o = o * R + e % R;
+        e /= R;
+    }
+    return o;
+}
+
+template <typename Real, int N, int R, int TPT, int T, bool INV, int ORDER>
+__global__ void __launch_bounds__(TPT * T)
+order_kernel(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __restrict__ twn, int64_t batch) {
+    using C = cplx<Real>;
+    constexpr int TS = ilog(N, R);  // stages
+    constexpr int NR = N / R, BPT = NR / TPT, NTH = TPT * T;
+    constexpr int LDSN = lds_len(N);
+    constexpr int NBUF = ORDER == ORDER_PEASE ? 2 : 1;
+    static_assert(NR % TPT == 0, "butterflies must split evenly");
+    __shared__ C lds[NBUF * T * LDSN];
+    const int tid = (int)threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * T;
+    const int count = (int)min((int64_t)T, batch - b0);
+    const int tr = tid / TPT, t = tid - tr * TPT;
+    // load: consecutive lanes on consecutive elements; CT writes the
+    // digit-reversed position
+    constexpr int TOT = T * N, IT = (TOT + NTH - 1) / NTH;
+    C buf[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int l = tid + i * NTH;
+        const int q = min(l / N, count - 1);  // clamped to a real transform
+        buf[i] = ld_in<INV>(in + (b0 + q) * N + (l % N));
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int l = tid + i * NTH;
+        if (l < TOT) {
+            const int e = l % N;
+            lds[(l / N) * LDSN + lds_pad(ORDER == ORDER_CT ? drev<R, TS>(e) : e)] = buf[i];
+        }
+    }
+    __syncthreads();
+    C* a = lds + tr * LDSN;
+    C* b = lds + (T + tr) * LDSN;  // Pease: second buffer
+#pragma unroll
+    for (int s = 0; s < TS; ++s) {
+        int m = 1;
+#pragma unroll
+        for (int u = 0; u < s; ++u) m *= R;
+        if constexpr (ORDER == ORDER_CT) {
+#pragma unroll
+            for (int i = 0; i < BPT; ++i) {
+                const int bf = t + i * TPT;
+                const int g = bf / m, k = bf - g * m;
+                const int base = g * m * R + k;
+                C v[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[r] = a[lds_pad(base + r * m)];
+                if (s > 0) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twn[r * k * (N / (m * R))]);
+                }
+                Codelet<R, C>::run(v);
+#pragma unroll
+                for (int r = 0; r < R; ++r) a[lds_pad(base + r * m)] = v[r];
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int i = 0; i < BPT; ++i) {
+                const int j = t + i * TPT;
+                C v[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[r] = a[lds_pad(j + r * NR)];
+                if (s > 0) {
+                    // reversal of the s low digits of j: reverse all TS digits of
+                    // (j mod m) < R^s, then drop the TS - s trailing zeros
+                    const int kk = drev<R, TS>(j % m) / (N / m);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twn[r * kk * (N / (m * R))]);
+                }
+                Codelet<R, C>::run(v);
+#pragma unroll
+                for (int r = 0; r < R; ++r) b[lds_pad(j * R + r)] = v[r];
+            }
+            __syncthreads();
+            C* tmp = a;
+            a = b;
+            b = tmp;
+        }
+    }
+    // store natural order; Pease reads the digit-reversed position
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int l = tid + i * NTH;
+        const int q = l / N, e = l % N;
+        if (l < TOT && q < count) {
+            C* src = (ORDER == ORDER_PEASE && (TS % 2 == 1)) ? lds + (T + q) * LDSN : lds + q * LDSN;
+            st_out<INV>(out + (b0 + q) * N + e, src[lds_pad(ORDER == ORDER_PEASE ? drev<R, TS>(e) : e)]);
+        }
+    }
+}
+
+template <typename Real, int N, int R, int ORDER>
+struct OrderInst {
+    static constexpr int BPT0 = kMaxElemsPerThread / R >= 1 ? kMaxElemsPerThread / R : 1;
+    static constexpr int TPT0 = (N / R) / BPT0 >= 1 ? (N / R) / BPT0 : 1;
+    static constexpr int TPT = TPT0 > 1024 ? 1024 : TPT0;
+    static constexpr int NBUF = ORDER == ORDER_PEASE ? 2 : 1;
+    static constexpr int CS = (int)sizeof(cplx<Real>);
+    static constexpr int T0 = TPT >= 256 ? 1 : 256 / TPT;
+    static constexpr int T = (T0 * NBUF * lds_len(N) * CS > kLdsMaxPerGroup) ? 1 : T0;
+    static_assert(NBUF * T * lds_len(N) * CS <= kLdsMaxPerGroup, "order kernel LDS");
+    static OrderEntry entry(int dtype) {
+        OrderEntry e{dtype, N, ORDER, R, TPT, T,
+                     reinterpret_cast<const void*>(&order_kernel<Real, N, R, TPT, T, false, ORDER>),
+                     reinterpret_cast<const void*>(&order_kernel<Real, N, R, TPT, T, true, ORDER>)};
+        return e;
+    }
+};
+
+}  // namespace fftc

@@ -40,12 +40,15 @@ struct fftc_plan_s {
     // layout plan: the compiled kernel with layout accessors, and the layouts
     bool has_layout = false;
     fftc_layout lin{}, lout{};
+    // order plan
+    const fftc::OrderEntry* order = nullptr;
 };
 
 namespace fftc {
 
 // `batch` <= p->batch: run the first `batch` transforms.
 fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);
+fftc_status launch_order(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);
 fftc_status launch_layout(const fftc_plan_s* p, const void* in_re, const void* in_im, void* out_re, void* out_im,
                           int64_t batch, hipStream_t s);
 fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);

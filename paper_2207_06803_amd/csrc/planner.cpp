@@ -133,12 +133,18 @@ std::vector<int> choose_radices(int64_t n, int dtype) {
 }
 
 // ---- tuning database ----------------------------------------------------------
-// Text file, one line per entry:  <arch> <c64|c128> <n> <r1,r2,...> <ms>
-// Entries for another architecture are ignored; a list that does not multiply
-// to n is ignored.
+// Text file, one line per entry:  <arch> <c64|c128> <n> [<order>:]<r1,r2,...> <ms>
+// with <order> "ct" or "pease" for an alternative order (its list is the
+// radix repeated), none for Stockham.  Entries for another architecture are
+// ignored; a list that does not multiply to n is ignored.
 namespace {
+struct TuneEntry {
+    std::vector<int> rs;
+    double ms;
+    int order;  // 0: Stockham
+};
 std::mutex g_tune_mu;
-std::map<std::pair<int64_t, int>, std::pair<std::vector<int>, double>> g_tune;
+std::map<std::pair<int64_t, int>, TuneEntry> g_tune;
 bool g_tune_env_done = false;
 const char* kTuneArch = "gfx950";
 
@@ -152,17 +158,29 @@ int load_locked(const char* path) {
     while (fscanf(f, "%63s %15s %lld %255s %lf", arch, dt, &n, rl, &ms) == 5) {
         if (strcmp(arch, kTuneArch) != 0) continue;
         const int dtype = strcmp(dt, "c128") == 0 ? FFTC_C128 : FFTC_C64;
+        int order = 0;
+        char* list = rl;
+        if (char* colon = strchr(rl, ':')) {
+            *colon = 0;
+            order = strcmp(rl, "ct") == 0 ? 1 : strcmp(rl, "pease") == 0 ? 2 : -1;
+            list = colon + 1;
+        }
+        if (order < 0) continue;
         std::vector<int> rs;
         int64_t prod = 1;
         bool ok = true;
-        for (char* tok = strtok(rl, ","); tok; tok = strtok(nullptr, ",")) {
+        for (char* tok = strtok(list, ","); tok; tok = strtok(nullptr, ",")) {
             const int r = atoi(tok);
             ok = ok && (r == 2 || r == 3 || r == 4 || r == 5 || r == 7 || r == 8 || r == 16);
             rs.push_back(r);
             prod *= r;
         }
-        if (ok && prod == n && (int)rs.size() <= kMaxStages) {
-            g_tune[{(int64_t)n, dtype}] = {rs, ms};
+        if (order > 0) {  // one radix repeated
+            for (int r : rs) ok = ok && r == rs[0];
+            ok = ok && !rs.empty() && find_order(dtype, n, order, rs[0]) != nullptr;
+        }
+        if (ok && prod == n && (order > 0 || (int)rs.size() <= kMaxStages)) {
+            g_tune[{(int64_t)n, dtype}] = {rs, ms, order};
             ++added;
         }
     }
@@ -178,19 +196,37 @@ void env_locked() {
 }
 }  // namespace
 
+bool tune_lookup_order(int64_t n, int dtype, int* order, int* radix) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    env_locked();
+    auto it = g_tune.find({n, dtype});
+    if (it == g_tune.end() || it->second.order == 0) return false;
+    *order = it->second.order;
+    *radix = it->second.rs[0];
+    return true;
+}
+
+void tune_record_order(int64_t n, int dtype, int order, int radix, double ms) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    env_locked();
+    std::vector<int> rs;
+    for (int64_t m = n; m > 1; m /= radix) rs.push_back(radix);
+    g_tune[{n, dtype}] = {rs, ms, order};
+}
+
 bool tune_lookup(int64_t n, int dtype, std::vector<int>* rs) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     env_locked();
     auto it = g_tune.find({n, dtype});
-    if (it == g_tune.end()) return false;
-    *rs = it->second.first;
+    if (it == g_tune.end() || it->second.order != 0) return false;  // Stockham entries only
+    *rs = it->second.rs;
     return true;
 }
 
 void tune_record(int64_t n, int dtype, const std::vector<int>& rs, double ms) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     env_locked();
-    g_tune[{n, dtype}] = {rs, ms};
+    g_tune[{n, dtype}] = {rs, ms, 0};
 }
 
 int tune_load_file(const char* path) {
@@ -206,9 +242,10 @@ int tune_save_file(const char* path) {
     for (auto& kv : g_tune) {
         fprintf(f, "%s %s %lld ", kTuneArch, kv.first.second == FFTC_C128 ? "c128" : "c64",
                 (long long)kv.first.first);
-        const auto& rs = kv.second.first;
+        if (kv.second.order) fprintf(f, "%s:", kv.second.order == 1 ? "ct" : "pease");
+        const auto& rs = kv.second.rs;
         for (size_t i = 0; i < rs.size(); ++i) fprintf(f, i ? ",%d" : "%d", rs[i]);
-        fprintf(f, " %.6f\n", kv.second.second);
+        fprintf(f, " %.6f\n", kv.second.ms);
     }
     fclose(f);
     return (int)g_tune.size();

@@ -35,6 +35,20 @@ const SpecEntry* find_layout(int dtype, int64_t n, const std::vector<int>& rs) {
 
 const FourStepEntry* fourstep_table_c64(int* count);
 const FourStepEntry* fourstep_table_c128(int* count);
+const OrderEntry* order_table_c64(int* count);
+const OrderEntry* order_table_c128(int* count);
+
+const OrderEntry* order_table(int dtype, int* count) {
+    return dtype == FFTC_C128 ? order_table_c128(count) : order_table_c64(count);
+}
+
+const OrderEntry* find_order(int dtype, int64_t n, int order, int radix) {
+    int cnt = 0;
+    const OrderEntry* tab = order_table(dtype, &cnt);
+    for (int i = 0; i < cnt; ++i)
+        if (tab[i].n == n && tab[i].order == order && tab[i].radix == radix) return &tab[i];
+    return nullptr;
+}
 
 const FourStepEntry* find_fourstep(int dtype, int64_t len, const std::vector<int>& rs) {
     int cnt = 0;

@@ -107,6 +107,65 @@ fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int* ra
     }
 }
 
+fftc_status fftc_autotune_orders(int64_t n, int64_t batch, int dtype, int reps, int* orders, int* radices,
+                                 double* us, int max, int* count, int* best) {
+    clear_error();
+    if (!count || !best || (max > 0 && (!orders || !radices || !us))) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
+    if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
+    if (batch < 1 || reps < 1) return fail(FFTC_ERR_INVALID_ARG, "batch and reps must be >= 1");
+    if (n < 2 || n > max_single_n(dtype) || !is_7smooth(n))
+        return fail(FFTC_ERR_UNSUPPORTED_SIZE, "autotune takes single-kernel lengths 2.." +
+                                                   std::to_string(max_single_n(dtype)));
+    try {
+        const size_t cs = dtype == FFTC_C128 ? 16 : 8;
+        const size_t bytes = (size_t)batch * (size_t)n * cs;
+        DeviceBuffers b;
+        FFTC_HIP_TRY(hipMalloc(&b.in, bytes));
+        FFTC_HIP_TRY(hipMalloc(&b.out, bytes));
+        FFTC_HIP_TRY(hipStreamCreate(&b.s));
+        FFTC_HIP_TRY(hipEventCreate(&b.e0));
+        FFTC_HIP_TRY(hipEventCreate(&b.e1));
+        FFTC_HIP_TRY(hipMemsetAsync(b.in, 0x3c, bytes, b.s));  // small finite values
+        // candidates: the Stockham plan, then every compiled order for n
+        std::vector<std::pair<int, int>> cands{{FFTC_ORDER_STOCKHAM, 0}};
+        int cnt = 0;
+        const OrderEntry* tab = order_table(dtype, &cnt);
+        for (int i = 0; i < cnt; ++i)
+            if (tab[i].n == n) cands.push_back({tab[i].order, tab[i].radix});
+        const std::vector<int> stock = choose_radices(n, dtype);
+        std::vector<double> times;
+        for (const auto& c : cands) {
+            fftc_plan_t p = nullptr;
+            fftc_status st = c.first == FFTC_ORDER_STOCKHAM
+                                 ? fftc_plan_radices(n, batch, FFTC_FORWARD, dtype, stock.data(), (int)stock.size(), &p)
+                                 : fftc_plan_order(n, batch, FFTC_FORWARD, dtype, c.first, c.second, &p);
+            if (st != FFTC_OK) return st;
+            double t = 0;
+            st = time_plan(p, b, reps, &t);
+            fftc_destroy_plan(p);
+            if (st != FFTC_OK) return st;
+            times.push_back(t);
+        }
+        size_t bi = 0;  // Stockham unless another order is faster by more than 1%
+        for (size_t i = 1; i < cands.size(); ++i)
+            if (times[i] < 0.99 * times[bi] && (bi != 0 || times[i] < 0.99 * times[0])) bi = i;
+        if (bi == 0)
+            tune_record(n, dtype, stock, times[0] * 1e-3);
+        else
+            tune_record_order(n, dtype, cands[bi].first, cands[bi].second, times[bi] * 1e-3);
+        *count = (int)cands.size();
+        *best = (int)bi;
+        for (int i = 0; i < (int)cands.size() && i < max; ++i) {
+            orders[i] = cands[i].first;
+            radices[i] = cands[i].second;
+            us[i] = times[i];
+        }
+        return FFTC_OK;
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_autotune_orders");
+    }
+}
+
 fftc_status fftc_tune_load(const char* path, int* entries) {
     clear_error();
     if (!path) return fail(FFTC_ERR_INVALID_ARG, "path is NULL");

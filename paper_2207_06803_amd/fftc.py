@@ -29,7 +29,13 @@ DTYPES = {"c64": C64, "complex64": C64, C64: C64, "c128": C128, "complex128": C1
           "f16": C64_F16, C64_F16: C64_F16}
 
 VARIANT_NAMES = {0: "single_specialised", 1: "single_generic", 2: "two_pass", 3: "mixed_persistent",
-                 4: "split_mfma", 5: "formula"}
+                 4: "split_mfma", 5: "formula", 6: "order"}
+
+# factorisation orders
+ORDER_STOCKHAM = 0
+ORDER_CT = 1
+ORDER_PEASE = 2
+ORDER_NAMES = {0: "stockham", 1: "ct", 2: "pease"}
 
 # formula plan flags
 FORMULA_NO_FOLD = 1
@@ -63,7 +69,8 @@ class PlanDesc(ctypes.Structure):
                 ("formula_passes", ctypes.c_int), ("formula_folded", ctypes.c_int),
                 ("formula_lds", ctypes.c_int), ("formula_fold_n", ctypes.c_int64),
                 ("formula_fold_p", ctypes.c_int64), ("formula_kernels", ctypes.c_int),
-                ("has_layout", ctypes.c_int), ("layout_in", Layout), ("layout_out", Layout)]
+                ("has_layout", ctypes.c_int), ("layout_in", Layout), ("layout_out", Layout),
+                ("order", ctypes.c_int), ("order_radix", ctypes.c_int)]
 
 
 _i64, _int, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
@@ -94,6 +101,12 @@ _SIGNATURES = {
     "fftc_plan_layout": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(Layout), ctypes.POINTER(Layout),
                                 ctypes.POINTER(_vp)]),
     "fftc_execute_layout": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "fftc_plan_order": (_int, [_i64, _i64, _int, _int, _int, _int, ctypes.POINTER(_vp)]),
+    "fftc_order_count": (_int, [_int]),
+    "fftc_order_entry": (_int, [_int, _int, ctypes.POINTER(_i64), ctypes.POINTER(_int), ctypes.POINTER(_int)]),
+    "fftc_autotune_orders": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                                    ctypes.POINTER(ctypes.c_double), _int, ctypes.POINTER(_int),
+                                    ctypes.POINTER(_int)]),
     "fftc_status_string": (ctypes.c_char_p, [_int]),
     "fftc_last_error": (ctypes.c_char_p, []),
 }
@@ -236,7 +249,8 @@ class Plan:
                 "formula_fold_p": d.formula_fold_p, "formula_kernels": d.formula_kernels,
                 "has_layout": bool(d.has_layout),
                 "layout_in": (d.layout_in.stride, d.layout_in.dist, d.layout_in.planar),
-                "layout_out": (d.layout_out.stride, d.layout_out.dist, d.layout_out.planar)}
+                "layout_out": (d.layout_out.stride, d.layout_out.dist, d.layout_out.planar),
+                "order": ORDER_NAMES.get(d.order, d.order), "order_radix": d.order_radix}
 
     def close(self) -> None:
         if self._h is not None and self._h.value:
@@ -312,6 +326,35 @@ def execute_layout(plan: Plan, in_re, in_im, out_re, out_im, stream=None) -> Non
     """Run a layout plan: planar sides give (re, im), interleaved sides (array, None)."""
     check(lib.fftc_execute_layout(plan._h, ptr(in_re), ptr(in_im) or None, ptr(out_re), ptr(out_im) or None,
                                   stream_handle(stream)), "fftc_execute_layout")
+
+
+def plan_order(n: int, batch: int, direction: int = FORWARD, dtype="c64", order=ORDER_CT, radix: int = 2) -> Plan:
+    """Plan running an alternative factorisation order (ORDER_CT / ORDER_PEASE)."""
+    h = _vp()
+    check(lib.fftc_plan_order(n, batch, direction, dtype_code(dtype), int(order), int(radix), ctypes.byref(h)),
+          "fftc_plan_order")
+    return Plan(n, batch, direction, dtype, _handle=h)
+
+
+def compiled_orders(dtype="c64"):
+    """(n, order, radix) of every compiled alternative-order kernel."""
+    code = dtype_code(dtype)
+    out = []
+    for i in range(lib.fftc_order_count(code)):
+        n, o, r = _i64(), _int(), _int()
+        check(lib.fftc_order_entry(code, i, ctypes.byref(n), ctypes.byref(o), ctypes.byref(r)), "fftc_order_entry")
+        out.append((n.value, o.value, r.value))
+    return out
+
+
+def autotune_orders(n: int, batch: int, dtype="c64", reps: int = 10):
+    """Time Stockham and every compiled order for n; returns ([(order, radix, us)], best index)."""
+    m = 64
+    orders, radices, us = (_int * m)(), (_int * m)(), (ctypes.c_double * m)()
+    cnt, best = _int(), _int()
+    check(lib.fftc_autotune_orders(n, batch, dtype_code(dtype), reps, orders, radices, us, m, ctypes.byref(cnt),
+                                   ctypes.byref(best)), "fftc_autotune_orders")
+    return [(ORDER_NAMES[orders[i]], radices[i], us[i]) for i in range(cnt.value)], best.value
 
 
 def autotune(n: int, batch: int, dtype="c64", reps: int = 10):
