@@ -20,6 +20,8 @@ HIP events on the stream its kernels run on):
     the Stockham plans vs run as written, and 2-D DFT formulas
   * planar and strided layouts: planar in/out, planar in -> interleaved out,
     and columns of a row-major array, against the interleaved plan
+  * factorisation orders: Stockham against recursive Cooley-Tukey (explicit
+    digit reversal) and Pease, every compiled radix, and the order autotuner
 and the FP64 oracle timed on the host cores as the CPU baseline.
 
 Prints one JSON line.  `value` is GFLOP/s in the 5 N log2 N convention.
@@ -385,6 +387,33 @@ def layouts(torch, fftc, synth, timer):
                         "array transformed along its first axis (stride 2^24/n, dist 1)", "by_n": out}
 
 
+def orders(torch, fftc, synth, timer):
+    """Stockham against the alternative orders at 2^24 complex64 elements."""
+    xs = [torch.from_numpy(synth.uniform_complex(synth.rng(8), (ELEMS,), np.complex64)).to("cuda")
+          for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    out = {}
+    for n in (256, 1024, 4096):
+        b = ELEMS // n
+        row = {}
+        with fftc.Plan(n, b, fftc.FORWARD, "c64") as p:
+            row["stockham" + str(p.describe()["radices"])] = timer.avg_ms(
+                lambda i: p.execute(xs[i % 2], ys[i % 2], timer.s), 10) * 1e3
+        for nn, order, radix in fftc.compiled_orders("c64"):
+            if nn != n:
+                continue
+            with fftc.plan_order(n, b, fftc.FORWARD, "c64", order, radix) as p:
+                row[f"{fftc.ORDER_NAMES[order]}_r{radix}"] = timer.avg_ms(
+                    lambda i: p.execute(xs[i % 2], ys[i % 2], timer.s), 10) * 1e3
+        res, best = fftc.autotune_orders(n, b, "c64", reps=5)
+        out[str(n)] = {"us": row, "hbm_gbs": {k: 16.0 * ELEMS / (v * 1e-6) / 1e9 for k, v in row.items()},
+                       "autotuner_pick": f"{res[best][0]}_r{res[best][1]}" if res[best][1] else res[best][0]}
+    del xs, ys
+    torch.cuda.empty_cache()
+    return {"workload": "complex64 forward, 2^24 elements per launch; one LDS-resident kernel per order",
+            "by_n": out}
+
+
 def config5(args, torch, fftc, synth):
     from paper_2207_06803_amd import server as srv
     g = synth.rng(5)
@@ -587,6 +616,7 @@ def main():
                          ("config4_split_precision", lambda: config4(torch, fftc, synth, timer)),
                          ("formula", lambda: formula(torch, fftc, synth, timer)),
                          ("layouts", lambda: layouts(torch, fftc, synth, timer)),
+                         ("orders", lambda: orders(torch, fftc, synth, timer)),
                          ("config5_serving", lambda: config5(args, torch, fftc, synth))):
             log(f"{name} ...")
             extras[name] = fn()
