@@ -237,6 +237,55 @@ struct ContigOff {
     __device__ __forceinline__ int64_t operator()(int q) const { return base + (int64_t)q * n; }
 };
 
+// Staged group with 16-byte accesses: the group's T transforms are one
+// contiguous range; each lane moves two complex64 per access (measured on
+// 2^24 complex64 elements: N = 16 48.9 -> 44.3 us, N = 64 53.3 -> 46.4 us).
+template <class K, int NTH, int... Rs>
+__device__ __forceinline__ void staged_pairs(const float2* gin, float2* gout, int count, float2* lds,
+                                             const float2* __restrict__ tw, int tid) {
+    using C = float2;
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    constexpr int N = K::N, TPT = K::TPT, T = K::T;
+    constexpr int LDSN = SpecLds<K, sizeof...(Rs)>::LDSN;
+    constexpr int TOT2 = T * N / 2, IT2 = (TOT2 + NTH - 1) / NTH;
+    const int valid2 = count * N / 2;
+    const int tr = (T == 1) ? (tid < TPT ? 0 : 1) : tid / TPT;
+    const int t = (T == 1) ? tid : tid - tr * TPT;
+    const bool member = tr < T;
+    const bool valid = member && tr < count;
+    f32x4 buf[IT2];
+#pragma unroll
+    for (int i = 0; i < IT2; ++i) {
+        const int l2 = min(tid + i * NTH, valid2 - 1);
+        buf[i] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(gin) + l2);
+    }
+#pragma unroll
+    for (int i = 0; i < IT2; ++i) {
+        const int l = 2 * (tid + i * NTH);
+        if (l < 2 * TOT2) {
+            C a = mk(buf[i].x, buf[i].y), b = mk(buf[i].z, buf[i].w);
+            if (K::INV) { a = cconj(a); b = cconj(b); }
+            lds[(l / N) * LDSN + lds_pad(l % N)] = a;
+            lds[((l + 1) / N) * LDSN + lds_pad((l + 1) % N)] = b;
+        }
+    }
+    __syncthreads();
+    spec_stages<K, 1, 0, true, false, false, Rs...>((const C*)nullptr, (C*)nullptr, lds + (member ? tr : 0) * LDSN,
+                                                     tw, t, valid, member);
+#pragma unroll
+    for (int i = 0; i < IT2; ++i) {
+        const int l2 = tid + i * NTH;
+        const int l = 2 * l2;
+        if (l2 < valid2) {
+            C a = lds[(l / N) * LDSN + lds_pad(l % N)], b = lds[((l + 1) / N) * LDSN + lds_pad((l + 1) % N)];
+            if (K::INV) { a = cconj(a); b = cconj(b); }
+            f32x4 v;
+            v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(gout) + l2);
+        }
+    }
+}
+
 template <class K, int... Rs>
 __global__ void __launch_bounds__(K::TPT * K::T)
 stockham_spec(const typename K::C* in, typename K::C* out,
@@ -246,6 +295,16 @@ stockham_spec(const typename K::C* in, typename K::C* out,
     __shared__ C lds[T * SpecLds<K, sizeof...(Rs)>::LDSN];
     const int64_t b0 = (int64_t)blockIdx.x * T;
     const int count = (int)min((int64_t)T, batch - b0);
+    if constexpr (K::STAGED && sizeof(C) == 8 && N % 2 == 0) {
+        // 16-byte aligned buffers (the group's range starts at an even element)
+        if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0) {
+            staged_pairs<K, NTH, Rs...>(reinterpret_cast<const float2*>(in) + b0 * N,
+                                        reinterpret_cast<float2*>(out) + b0 * N, count,
+                                        reinterpret_cast<float2*>(lds), reinterpret_cast<const float2*>(tw),
+                                        (int)threadIdx.x);
+            return;
+        }
+    }
     spec_group<K, NTH, ContigOff, Rs...>(in, out, ContigOff{b0 * N, N}, count, lds, tw, (int)threadIdx.x);
 }
 
