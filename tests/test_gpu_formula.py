@@ -210,3 +210,27 @@ def test_plan_errors():
         fftc.plan_formula("DFT(4)", 0)
     with pytest.raises(fftc.FFTCError):
         fftc.plan_formula("DFT(1048576) ⊗ I(2)", 1 << 11)  # batch * dim >= 2^31
+
+
+@pytest.mark.parametrize("text,flags", [
+    (formulas.recursive_ct(1024, (2,)), NO_FOLD),
+    (formulas.recursive_ct(1024, (16, 4)), NO_FOLD),
+    ("DFT(1024)", NO_FOLD | EQ2),
+    (formulas.dft2d(64, 64), 0),
+    (formulas.dft2d(128, 128), 0),
+    (formulas.dft2d(1024, 1024), 0),
+], ids=["rct1024_r2_as_written", "rct1024_r16_as_written", "dft1024_eq2", "dft2d_64", "dft2d_128", "dft2d_1024"])
+def test_full_size_sampled(text, flags):
+    # the launch the benchmark times (2^24 complex64 elements); sampled vectors
+    # (first, middle, last) against the formula oracle
+    dim = of.size(of.parse(text))
+    b = (1 << 24) // dim
+    g = synth.rng(127, dim % 1021, flags)
+    x = synth.uniform_complex(g, (b, dim), np.complex64)
+    say(f"full size {text[:50]!r} dim={dim} batch={b}")
+    with fftc.plan_formula(text, b, FWD, "c64", flags) as p:
+        y = run(p, x)
+    rows = sorted({0, b // 2, b - 1})
+    want = of.apply(text, x[rows])
+    err = rel_l2(y[rows], want)
+    assert err.max() <= tol(text, dim, "c64"), err

@@ -206,3 +206,36 @@ def test_execute_errors():
             fftc.execute_layout(p, a, c, a, a)          # partial overlap
         with pytest.raises(fftc.FFTCError):
             p.execute(a, c)                             # planar plans need execute_layout
+
+
+@pytest.mark.parametrize("n", [256, 1024, 4096])
+def test_full_size_sampled(n):
+    # the benchmark's launches (2^24 complex64 elements): planar rows and
+    # columns of the n x (2^24 / n) row-major array; sampled transforms
+    E = 1 << 24
+    b = E // n
+    g = synth.rng(136, n)
+    host = synth.uniform_complex(g, (E,), np.complex64)
+    picks = sorted({0, 1, b // 2, b - 1})
+    # planar rows: transform q is host[q n : (q + 1) n]
+    re = torch.from_numpy(np.ascontiguousarray(host.real)).cuda()
+    im = torch.from_numpy(np.ascontiguousarray(host.imag)).cuda()
+    ore, oim = torch.empty_like(re), torch.empty_like(im)
+    say(f"full-size planar n={n}")
+    with fftc.plan_layout(n, b, FWD, "c64", (1, n, 1), (1, n, 1)) as p:
+        fftc.execute_layout(p, re, im, ore, oim)
+    torch.cuda.synchronize()
+    y = (ore.cpu().numpy() + 1j * oim.cpu().numpy()).reshape(b, n)
+    x = host.reshape(b, n)
+    assert rel_l2(y[picks], oracle.dft(x[picks])).max() <= tol_for(n, "c64")
+    del re, im, ore, oim
+    # columns: transform q is host[q + j b]
+    xd = torch.from_numpy(host).cuda()
+    yd = torch.empty_like(xd)
+    say(f"full-size columns n={n}")
+    with fftc.plan_layout(n, b, FWD, "c64", (b, 1, 0), (b, 1, 0)) as p:
+        fftc.execute_layout(p, xd, None, yd, None)
+    torch.cuda.synchronize()
+    yc = yd.cpu().numpy().reshape(n, b)
+    xc = host.reshape(n, b)
+    assert rel_l2(yc[:, picks].T, oracle.dft(np.ascontiguousarray(xc[:, picks].T))).max() <= tol_for(n, "c64")

@@ -56,3 +56,19 @@ def test_autotune_orders_and_recorded_order(tmp_path):
         assert rel_l2(y, oracle.dft(x)).max() <= tol_for(256, "c64")
     finally:
         fftc.tune_clear()
+
+
+@pytest.mark.parametrize("n", [256, 1024, 4096])
+def test_full_size_sampled(n):
+    # the benchmark's launches: 2^24 complex64 elements, every compiled order
+    b = (1 << 24) // n
+    x = synth.uniform_complex(synth.rng(142, n), (b, n), np.complex64)
+    picks = sorted({0, 1, b // 2, b - 1})
+    want = oracle.dft(x[picks])
+    for nn, order, radix in fftc.compiled_orders("c64"):
+        if nn != n:
+            continue
+        say(f"full-size order n={n} {fftc.ORDER_NAMES[order]} r={radix}")
+        with fftc.plan_order(n, b, FWD, "c64", order, radix) as p:
+            y = run_plan(p, x)
+        assert rel_l2(y[picks], want).max() <= tol_for(n, "c64"), (order, radix)
