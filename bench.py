@@ -15,7 +15,9 @@ HIP events on the stream its kernels run on):
     per-length path (37 batched launches, graph-captured)
   * split-precision MFMA modes at N = 1024, 4096, 16384, batch 8192: time and
     error against the complex128 GPU path
-  * serving: 20,000 Poisson-arriving requests, p50/p99 latency
+  * serving: 20,000 Poisson-arriving requests, p50/p99 latency, with and
+    without fusing same-length requests into one launch, at the configured
+    rate and at four times it
   * formula plans (the Kronecker-product DSL): Eq. 2 programs folded onto
     the Stockham plans vs run as written, and 2-D DFT formulas
   * planar and strided layouts: planar in/out, planar in -> interleaved out,
@@ -414,43 +416,52 @@ def orders(torch, fftc, synth, timer):
             "by_n": out}
 
 
-def config5(args, torch, fftc, synth):
+def config5(args, torch, fftc, synth, fuse=True, rate=None):
     from paper_2207_06803_amd import server as srv
+    rate = rate or args.serve_rate
     g = synth.rng(5)
-    reqs = synth.serving_requests(synth.rng(5, 99), args.serve_requests, args.serve_rate)
+    reqs = synth.serving_requests(synth.rng(5, 99), args.serve_requests, rate)
     pool_elems = (1 << 24) + (1 << 20)
     pool = torch.from_numpy(synth.uniform_complex(g, (pool_elems,), np.complex64)).to("cuda")
     offs = g.integers(0, (1 << 20), size=args.serve_requests)
     budget = 64 << 30
-    srv.start(budget, n_streams=4, max_inflight=64)
+    srv.start(budget, n_streams=4, max_inflight=64, fuse=fuse)
     try:
         for n in sorted(set(int(v) for v in reqs["n"])):
             for d in (fftc.FORWARD, fftc.INVERSE):
                 srv.prepare(n, d, "c64", 256)
         torch.cuda.synchronize()
-        N = args.serve_requests
         base = pool.data_ptr()
-        t0 = srv.now_ns() + 2_000_000
-        sched = t0 + (reqs["arrival_s"] * 1e9).astype(np.int64)
-        done = {}
-        i = 0
-        last = srv.now_ns()
-        while len(done) < N:
-            now = srv.now_ns()
-            if now - last > 60_000_000_000:
-                raise RuntimeError(f"serving made no progress for 60 s ({len(done)} of {N} done)")
-            while i < N and sched[i] <= now:
-                rc = srv.submit(int(reqs["n"][i]), int(reqs["batch"][i]), int(reqs["direction"][i]),
-                                base + 8 * int(offs[i]), i, int(sched[i]))
-                if rc != 0:
-                    raise RuntimeError(f"submit failed with status {rc}")
-                i += 1
-            for c in srv.poll():
-                if c["status"] != 0:
-                    raise RuntimeError(f"request {c['tag']} failed: {c['status']}")
-                done[c["tag"]] = c
-                srv.release(c["out"])
-                last = now
+
+        def serve(N, tag0=0):
+            t0 = srv.now_ns() + 2_000_000
+            sched = t0 + (reqs["arrival_s"][:N] * 1e9).astype(np.int64)
+            done = {}
+            i = 0
+            last = srv.now_ns()
+            while len(done) < N:
+                now = srv.now_ns()
+                if now - last > 60_000_000_000:
+                    raise RuntimeError(f"serving made no progress for 60 s ({len(done)} of {N} done)")
+                while i < N and sched[i] <= now:
+                    rc = srv.submit(int(reqs["n"][i]), int(reqs["batch"][i]), int(reqs["direction"][i]),
+                                    base + 8 * int(offs[i]), tag0 + i, int(sched[i]))
+                    if rc != 0:
+                        raise RuntimeError(f"submit failed with status {rc}")
+                    i += 1
+                for c in srv.poll():
+                    if c["status"] != 0:
+                        raise RuntimeError(f"request {c['tag']} failed: {c['status']}")
+                    done[c["tag"] - tag0] = c
+                    srv.release(c["out"])
+                    last = now
+            return sched, done
+
+        # untimed warm-up on the first tenth of the stream (clocks, caches)
+        serve(max(1, args.serve_requests // 10), tag0=1 << 40)
+        st0 = srv.stats()
+        N = args.serve_requests
+        sched, done = serve(N)
         st = srv.stats()
     finally:
         srv.stop(drain=False)
@@ -459,8 +470,12 @@ def config5(args, torch, fftc, synth):
     fl = float(sum(flops(int(n), int(b)) for n, b in zip(reqs["n"], reqs["batch"])))
     by = float(sum(16.0 * int(n) * int(b) for n, b in zip(reqs["n"], reqs["batch"])))
     span = (max(c["done_ns"] for c in done.values()) - min(int(s) for s in sched)) * 1e-9
-    return {"workload": f"{N} complex64 requests, Poisson arrivals at {args.serve_rate:.0f}/s, "
-                        "batch U[1,256], N in 2^6..2^16, half forward / half inverse, budget 64 GiB",
+    return {"workload": f"{N} complex64 requests, Poisson arrivals at {rate:.0f}/s, "
+                        "batch U[1,256], N in 2^6..2^16, half forward / half inverse, budget 64 GiB, "
+                        + ("same-length requests admitted together fused into one launch" if fuse
+                           else "one launch per request"),
+            "fused_launches": st["fused_launches"] - st0["fused_launches"],
+            "fused_requests": st["fused_requests"] - st0["fused_requests"],
             "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
             "mean_us": float(lat.mean()), "max_us": float(lat.max()),
             "queue_p99_us": float(np.percentile(q, 99)),
@@ -617,7 +632,11 @@ def main():
                          ("formula", lambda: formula(torch, fftc, synth, timer)),
                          ("layouts", lambda: layouts(torch, fftc, synth, timer)),
                          ("orders", lambda: orders(torch, fftc, synth, timer)),
-                         ("config5_serving", lambda: config5(args, torch, fftc, synth))):
+                         ("config5_serving", lambda: config5(args, torch, fftc, synth)),
+                         ("config5_serving_unfused", lambda: config5(args, torch, fftc, synth, fuse=False)),
+                         ("serving_4x_rate", lambda: config5(args, torch, fftc, synth, rate=4 * args.serve_rate)),
+                         ("serving_4x_rate_unfused",
+                          lambda: config5(args, torch, fftc, synth, fuse=False, rate=4 * args.serve_rate))):
             log(f"{name} ...")
             extras[name] = fn()
     cpu = None

@@ -350,6 +350,10 @@ typedef struct {
                               use and no computation, for testing the admission
                               and scheduling logic on a host without a GPU */
     int64_t mock_ns_per_mb;/* mock executor: simulated time per MiB of output */
+    int fuse;              /* 1: requests admitted together that share (n, direction,
+                              dtype) run as one launch (up to 16 per launch) when the
+                              length has a several-requests kernel (powers of two with
+                              the preferred radix list); 0: one launch per request */
 } fftc_server_config;
 
 typedef struct {
@@ -374,17 +378,21 @@ typedef struct {
     int64_t submitted, admitted, completed, rejected, cancelled, failed;
     size_t budget_bytes, bytes_in_use, peak_bytes;
     int pending, inflight, max_inflight_seen;
+    int64_t fused_launches, fused_requests;  /* several-requests launches and the requests they ran */
 } fftc_server_stats;
 
 /* Monotonic clock (ns) used for all server timestamps. */
 int64_t fftc_now_ns(void);
 
-/* Start the server on the current device: allocates the budget arena, the
- * streams and events.  Fails if a server is already running. */
+/* Start the server on the current device: allocates the budget arena (and
+ * writes it once, so requests never meet untouched memory), the streams and
+ * events.  Fails if a server is already running. */
 fftc_status fftc_server_start(const fftc_server_config *cfg);
 
 /* Build (and keep) the plan for (n, direction, dtype) able to run batches up
- * to max_batch, so the first request of that shape pays no planning cost. */
+ * to max_batch, and run it once on a scratch buffer of its own (with the
+ * several-requests kernel too when fusing), so the first request of that
+ * shape pays neither planning nor kernel loading.  Synchronous. */
 fftc_status fftc_server_prepare(int64_t n, int direction, int dtype, int64_t max_batch);
 
 /* Queue a request (copied); returns at once.  FFTC_ERR_TOO_LARGE if its

@@ -153,6 +153,16 @@ static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* o
     return FFTC_OK;
 }
 
+fftc_status launch_reqs(const SpecEntry* e, bool inv, const ReqList& list, int64_t groups, const void* tw,
+                        hipStream_t s) {
+    ReqList l = list;
+    const void* t = tw;
+    void* args[] = {(void*)&l, (void*)&t};
+    hipError_t err = hipLaunchKernel(inv ? e->inv : e->fwd, dim3((unsigned)groups), dim3(e->tpt * e->t), args, 0, s);
+    if (err != hipSuccess) return fail_hip(err, "hipLaunchKernel(stockham_spec_reqs)");
+    return FFTC_OK;
+}
+
 fftc_status launch_order(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s) {
     const OrderEntry* o = p->order;
     const int64_t groups = (batch + o->t - 1) / o->t;

@@ -64,6 +64,8 @@ const SpecEntry* find_spec(int dtype, int64_t n, const std::vector<int>& rs);
 // The same transforms compiled with the layout accessors (planar / strided
 // data): the preferred list of every compiled length.
 const SpecEntry* find_layout(int dtype, int64_t n, const std::vector<int>& rs);
+// Several-requests kernels (one launch for requests of one length).
+const SpecEntry* find_serve(int dtype, int64_t n, const std::vector<int>& rs);
 
 // Two-pass column kernels with compiled bodies (fourstep_c64/c128.hip):
 // the four kernels (pass x direction) of one column length.

@@ -17,6 +17,22 @@ const SpecEntry* spec_part(int dtype, int part, int* count) {
     return dtype == FFTC_C128 ? c128[part](count) : c64[part](count);
 }
 
+const SpecEntry* serve_table_c64(int* count);
+const SpecEntry* serve_table_c128(int* count);
+
+const SpecEntry* find_serve(int dtype, int64_t n, const std::vector<int>& rs) {
+    int cnt = 0;
+    const SpecEntry* tab = dtype == FFTC_C128 ? serve_table_c128(&cnt) : serve_table_c64(&cnt);
+    for (int i = 0; i < cnt; ++i) {
+        const SpecEntry& e = tab[i];
+        if (e.n != n || e.nr != (int)rs.size()) continue;
+        bool same = true;
+        for (int q = 0; q < e.nr; ++q) same = same && e.radices[q] == rs[q];
+        if (same) return &e;
+    }
+    return nullptr;
+}
+
 const SpecEntry* layout_table_c64(int* count);
 const SpecEntry* layout_table_c128(int* count);
 

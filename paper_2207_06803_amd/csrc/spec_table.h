@@ -24,6 +24,12 @@ struct SpecInst {
                     reinterpret_cast<const void*>(&stockham_spec<KI, Rs...>), id};
         return e;
     }
+    static SpecEntry reqs_entry(int dtype) {
+        SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
+                    reinterpret_cast<const void*>(&stockham_spec_reqs<KF, Rs...>),
+                    reinterpret_cast<const void*>(&stockham_spec_reqs<KI, Rs...>), -1};
+        return e;
+    }
     static SpecEntry layout_entry(int dtype) {
         SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
                     reinterpret_cast<const void*>(&stockham_spec_layout<KF, Rs...>),

@@ -286,15 +286,12 @@ __device__ __forceinline__ void staged_pairs(const float2* gin, float2* gout, in
     }
 }
 
+// Transforms b0 .. b0 + count - 1 of contiguous batch-major data.
 template <class K, int... Rs>
-__global__ void __launch_bounds__(K::TPT * K::T)
-stockham_spec(const typename K::C* in, typename K::C* out,
-              const typename K::C* __restrict__ tw, int64_t batch) {
+__device__ __forceinline__ void spec_contig(const typename K::C* in, typename K::C* out, int64_t b0, int count,
+                                            typename K::C* lds, const typename K::C* __restrict__ tw) {
     using C = typename K::C;
-    constexpr int N = K::N, T = K::T, NTH = K::TPT * K::T;
-    __shared__ C lds[T * SpecLds<K, sizeof...(Rs)>::LDSN];
-    const int64_t b0 = (int64_t)blockIdx.x * T;
-    const int count = (int)min((int64_t)T, batch - b0);
+    constexpr int N = K::N, NTH = K::TPT * K::T;
     if constexpr (K::STAGED && sizeof(C) == 8 && N % 2 == 0) {
         // 16-byte aligned buffers (the group's range starts at an even element)
         if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0) {
@@ -306,6 +303,44 @@ stockham_spec(const typename K::C* in, typename K::C* out,
         }
     }
     spec_group<K, NTH, ContigOff, Rs...>(in, out, ContigOff{b0 * N, N}, count, lds, tw, (int)threadIdx.x);
+}
+
+template <class K, int... Rs>
+__global__ void __launch_bounds__(K::TPT * K::T)
+stockham_spec(const typename K::C* in, typename K::C* out,
+              const typename K::C* __restrict__ tw, int64_t batch) {
+    using C = typename K::C;
+    constexpr int T = K::T;
+    __shared__ C lds[T * SpecLds<K, sizeof...(Rs)>::LDSN];
+    const int64_t b0 = (int64_t)blockIdx.x * T;
+    const int count = (int)min((int64_t)T, batch - b0);
+    spec_contig<K, Rs...>(in, out, b0, count, lds, tw);
+}
+
+// Several requests of one length in one launch (the serving runtime's fused
+// steps): request r has its own in / out and batch; its workgroups are
+// gstart[r] .. gstart[r + 1] - 1.
+constexpr int kMaxFused = 16;
+struct ReqList {
+    const void* in[kMaxFused];
+    void* out[kMaxFused];
+    int64_t batch[kMaxFused];
+    int64_t gstart[kMaxFused + 1];
+    int count;
+};
+
+template <class K, int... Rs>
+__global__ void __launch_bounds__(K::TPT * K::T)
+stockham_spec_reqs(ReqList L, const typename K::C* __restrict__ tw) {
+    using C = typename K::C;
+    constexpr int T = K::T;
+    __shared__ C lds[T * SpecLds<K, sizeof...(Rs)>::LDSN];
+    const int64_t blk = blockIdx.x;
+    int r = 0;
+    while (r + 1 < L.count && L.gstart[r + 1] <= blk) ++r;
+    const int64_t b0 = (blk - L.gstart[r]) * T;
+    const int count = (int)min((int64_t)T, L.batch[r] - b0);
+    spec_contig<K, Rs...>(static_cast<const C*>(L.in[r]), static_cast<C*>(L.out[r]), b0, count, lds, tw);
 }
 
 // The same transform for any other layout (GAcc): transform q of the

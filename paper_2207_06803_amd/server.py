@@ -12,7 +12,7 @@ EXECUTOR_MOCK = 1
 
 class Config(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("n_streams", _int), ("max_inflight", _int),
-                ("executor", _int), ("mock_ns_per_mb", _i64)]
+                ("executor", _int), ("mock_ns_per_mb", _i64), ("fuse", _int)]
 
 
 class Request(ctypes.Structure):
@@ -29,7 +29,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("submitted", _i64), ("admitted", _i64), ("completed", _i64), ("rejected", _i64),
                 ("cancelled", _i64), ("failed", _i64), ("budget_bytes", ctypes.c_size_t),
                 ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("pending", _int),
-                ("inflight", _int), ("max_inflight_seen", _int)]
+                ("inflight", _int), ("max_inflight_seen", _int), ("fused_launches", _i64),
+                ("fused_requests", _i64)]
 
 
 fftc.register("fftc_now_ns", _i64, [])
@@ -49,8 +50,8 @@ def now_ns() -> int:
 
 
 def start(budget_bytes: int, n_streams: int = 4, max_inflight: int = 64,
-          executor: int = EXECUTOR_GPU, mock_ns_per_mb: int = 0) -> None:
-    cfg = Config(budget_bytes, n_streams, max_inflight, executor, mock_ns_per_mb)
+          executor: int = EXECUTOR_GPU, mock_ns_per_mb: int = 0, fuse: bool = False) -> None:
+    cfg = Config(budget_bytes, n_streams, max_inflight, executor, mock_ns_per_mb, 1 if fuse else 0)
     check(lib.fftc_server_start(ctypes.byref(cfg)), "fftc_server_start")
 
 

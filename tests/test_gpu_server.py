@@ -60,8 +60,9 @@ def gpu_server():
             pass
 
 
-def test_results_in_the_mix_equal_results_alone(gpu_server):
-    gpu_server(1 << 30, n_streams=4, max_inflight=32)
+@pytest.mark.parametrize("fuse", [False, True])
+def test_results_in_the_mix_equal_results_alone(gpu_server, fuse):
+    gpu_server(1 << 30, n_streams=4, max_inflight=32, fuse=fuse)
     g = synth.rng(5, 1)
     pool = torch.from_numpy(synth.uniform_complex(g, (1 << 21,), np.complex64)).to("cuda")
     reqs = []
@@ -101,7 +102,12 @@ def test_results_in_the_mix_equal_results_alone(gpu_server):
                 ref = oracle.dft_points(rows[0], ks, d)
                 scale = np.sqrt(n * (np.abs(rows[0].astype(np.complex128)) ** 2).sum())
                 assert np.linalg.norm(y[:n][ks] - ref) / (scale * np.sqrt(len(ks) / n)) <= tol_for(n, "c64")
-    say("served", len(reqs), "stats", srv.stats())
+    st = srv.stats()
+    say("served", len(reqs), "fuse", fuse, "stats", st)
+    if fuse:  # a burst of 120 requests over 11 lengths: some steps run several requests
+        assert st["fused_launches"] > 0 and st["fused_requests"] >= 2 * st["fused_launches"]
+    else:
+        assert st["fused_launches"] == 0
 
 
 def test_small_budget_queues_and_holds(gpu_server):
