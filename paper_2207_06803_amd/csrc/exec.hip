@@ -126,6 +126,8 @@ static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* o
     C* tout = static_cast<C*>(out);
     const C* tw = static_cast<const C*>(p->tw);
     const bool inv = p->direction == FFTC_INVERSE;
+    if (!grid_fits((batch + p->t - 1) / std::max(p->t, 1)))
+        return fail(FFTC_ERR_INVALID_ARG, "batch too large for one launch");
     if (p->spec) {
         const int64_t groups = (batch + p->spec->t - 1) / p->spec->t;
         void* args[] = {(void*)&tin, (void*)&tout, (void*)&tw, (void*)&batch};
@@ -155,6 +157,7 @@ static fftc_status launch_single_t(const fftc_plan_s* p, const void* in, void* o
 
 fftc_status launch_reqs(const SpecEntry* e, bool inv, const ReqList& list, int64_t groups, const void* tw,
                         hipStream_t s) {
+    if (!grid_fits(groups)) return fail(FFTC_ERR_INVALID_ARG, "requests too large for one launch");
     ReqList l = list;
     const void* t = tw;
     void* args[] = {(void*)&l, (void*)&t};
@@ -166,6 +169,7 @@ fftc_status launch_reqs(const SpecEntry* e, bool inv, const ReqList& list, int64
 fftc_status launch_order(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s) {
     const OrderEntry* o = p->order;
     const int64_t groups = (batch + o->t - 1) / o->t;
+    if (!grid_fits(groups)) return fail(FFTC_ERR_INVALID_ARG, "batch too large for one launch");
     const void* tw = p->tw;
     void* args[] = {(void*)&in, (void*)&out, (void*)&tw, (void*)&batch};
     hipError_t e = hipLaunchKernel(p->direction == FFTC_INVERSE ? o->inv : o->fwd, dim3((unsigned)groups),
@@ -201,6 +205,7 @@ fftc_status launch_layout(const fftc_plan_s* p, const void* in_re, const void* i
     const int per = tile ? p->spec->tile_tc : p->spec->t;
     const int threads = tile ? p->spec->tile_tpt * p->spec->tile_tc : p->spec->tpt * p->spec->t;
     const int64_t groups = (batch + per - 1) / per;
+    if (!grid_fits(groups)) return fail(FFTC_ERR_INVALID_ARG, "batch too large for one launch");
     const void* fn = tile ? (inv ? p->spec->tile_inv : p->spec->tile_fwd) : (inv ? p->spec->inv : p->spec->fwd);
     hipError_t e;
     if (p->dtype == FFTC_C128) {

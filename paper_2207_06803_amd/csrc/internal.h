@@ -16,6 +16,9 @@ fftc_status fail(fftc_status s, const std::string& msg);
 fftc_status fail_hip(hipError_t e, const char* what);
 void clear_error();
 
+// A launch's workgroup count must fit the grid's x dimension.
+inline bool grid_fits(int64_t groups) { return groups >= 0 && groups <= 0x7fffffff; }
+
 #define FFTC_HIP_TRY(call)                                   \
     do {                                                     \
         hipError_t e_ = (call);                              \
