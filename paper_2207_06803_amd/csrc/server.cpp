@@ -249,8 +249,8 @@ class Server {
             retired_.clear();
         }
         if (!mock_) {
-            for (auto e : events_) hipEventDestroy(e);
-            for (auto s : streams_) hipStreamDestroy(s);
+            for (auto e : events_) (void)hipEventDestroy(e);
+            for (auto s : streams_) (void)hipStreamDestroy(s);
             if (base_ && hipFree(base_) != hipSuccess) st = fail(FFTC_ERR_HIP, "hipFree(arena)");
         }
         events_.clear();
@@ -395,7 +395,7 @@ class Server {
     }
 
     void loop() {
-        if (!mock_) hipSetDevice(device_);
+        if (!mock_) (void)hipSetDevice(device_);
         std::vector<int> free_slots;
         for (int i = cfg_.max_inflight - 1; i >= 0; --i) free_slots.push_back(i);
         std::vector<std::pair<InFlight, int>> running;
