@@ -59,6 +59,7 @@ struct SpecEntry {
     const void* tile_fwd = nullptr;
     const void* tile_inv = nullptr;
     int tile_tpt = 0, tile_tc = 0;
+    int tm = 0;  // transforms per 256-thread workgroup in the mixed kernel's body
 };
 // Compiled specialisations, in kSpecParts translation units per dtype.
 constexpr int kSpecParts = 4;

@@ -40,13 +40,16 @@ constexpr int round_tpt(int x) {
 // complex64 elements: N = 1024 51.5 -> 46.9 us, N = 64 46.5 -> 44.4 us, no
 // change at 4096 and up); N = 128, 256 keep 256-thread groups.
 constexpr int wg_target(int n) { return (n >= 512 || n <= 64) ? 64 : kWorkgroupTarget; }
-constexpr int pick_t(int tpt, int n, int csize, bool multi_stage) {
-    const int target = wg_target(n);
+// Transforms per workgroup for a given thread target.
+constexpr int pick_t_for(int target, int tpt, int n, int csize, bool multi_stage) {
     if (tpt >= target || (target % tpt) != 0) return 1;
     int t = target / tpt;
     const int per = multi_stage ? lds_len(n) * csize : 0;
     while (t > 1 && t * per > kLdsBudgetPerGroup) t >>= 1;
     return t;
+}
+constexpr int pick_t(int tpt, int n, int csize, bool multi_stage) {
+    return pick_t_for(wg_target(n), tpt, n, csize, multi_stage);
 }
 
 }  // namespace fftc

@@ -18,7 +18,7 @@ extern "C" __shared__ __align__(16) unsigned char fftc_dyn_lds[];
 
 #define FFTC_BODY_CASE(ID, N, ...)                                                                   \
     case ID:                                                                                         \
-        spec_body<typename SpecInst<Real, N, __VA_ARGS__>::template K<INV>, kMixedThreads, __VA_ARGS__>( \
+        spec_body<typename SpecInst<Real, N, __VA_ARGS__>::template KM<INV>, kMixedThreads, __VA_ARGS__>( \
             in, out, offsets + item.first, item.count, lds, twc, (int)threadIdx.x);                  \
         break;
 

@@ -18,10 +18,14 @@ struct SpecInst {
     using KF = SpecCfg<Real, N, TPT, T, false>;
     using KI = SpecCfg<Real, N, TPT, T, true>;
     template <bool INV> using K = typename std::conditional<INV, KI, KF>::type;
+    // bodies of the persistent mixed kernel: 256-thread workgroups
+    static constexpr int TM = pick_t_for(kWorkgroupTarget, TPT, N, (int)sizeof(cplx<Real>), NR > 1);
+    template <bool INV> using KM = SpecCfg<Real, N, TPT, TM, INV>;
     static SpecEntry entry(int dtype, int id) {
         SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
                     reinterpret_cast<const void*>(&stockham_spec<KF, Rs...>),
                     reinterpret_cast<const void*>(&stockham_spec<KI, Rs...>), id};
+        e.tm = TM;
         return e;
     }
     static SpecEntry reqs_entry(int dtype) {
