@@ -9,6 +9,7 @@ so the 256 MB last-level cache cannot serve the reads.
 
 The same JSON line carries the other workloads as extras (each timed with
 HIP events on the stream its kernels run on):
+  * a plain device copy over the same rotating buffers (for scale)
   * 64-point complex64, 1024 transforms: time per launch
   * complex128 at the headline sizes
   * 10,000 mixed-length transforms: one persistent launch (hipGraph) vs the
@@ -322,6 +323,19 @@ def config4(torch, fftc, synth, timer):
                         "per transform against the complex128 GPU path", "by_n": out}
 
 
+def copy_ceiling(torch, synth, timer):
+    """What a plain device copy reaches over the same rotating 1 GiB of
+    buffers as the headline (torch's copy kernel, 128 MiB in + 128 MiB out)."""
+    xs = [torch.from_numpy(synth.uniform_complex(synth.rng(9), (ELEMS,), np.complex64)).to("cuda")
+          for _ in range(NBUF)]
+    ys = [torch.empty_like(xs[0]) for _ in range(NBUF)]
+    avg = timer.avg_ms(lambda i: ys[i % NBUF].copy_(xs[i % NBUF]), 20)
+    del xs, ys
+    torch.cuda.empty_cache()
+    return {"workload": "torch copy_ of 2^24 complex64 over 4 rotating buffer pairs", "us": avg * 1e3,
+            "gbs": 16.0 * ELEMS / (avg * 1e-3) / 1e9}
+
+
 def formula(torch, fftc, synth, timer):
     """Formula plans at 2^24 complex64 elements per launch."""
     from paper_2207_06803_amd import formulas as F
@@ -624,7 +638,8 @@ def main():
                 "n": n_dom}
     extras = {}
     if not args.only_headline:
-        for name, fn in (("config1_n64", lambda: config1(torch, fftc, synth, timer)),
+        for name, fn in (("copy_ceiling", lambda: copy_ceiling(torch, synth, timer)),
+                         ("config1_n64", lambda: config1(torch, fftc, synth, timer)),
                          ("c128", lambda: c128(torch, fftc, synth, timer)),
                          ("two_pass", lambda: two_pass(torch, fftc, synth, timer)),
                          ("config3_mixed", lambda: config3(torch, fftc, synth, timer)),
