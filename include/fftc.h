@@ -132,9 +132,14 @@ typedef struct {
  * Plan for `batch` transforms of length n reading the `in` layout and
  * writing the `out` layout (NULL = interleaved, stride 1, dist n).
  * complex64 or complex128, single-kernel lengths (fftc_max_single_n) that
- * have a compiled kernel (every length of fftc_compiled_entry);
- * UNSUPPORTED_SIZE otherwise, INVALID_ARG for a bad or self-overlapping
- * layout.  No device allocation besides the twiddle table.
+ * have a compiled kernel (every length of fftc_compiled_entry).  Column-like
+ * layouts (dist < stride on either side) of lengths above 2048 (complex64)
+ * or 1024 (complex128), and of any 7-smooth length n = m k up to 2^20 with
+ * both factors <= 1024 compiled as two-pass column lengths, run as two
+ * passes of Eq. 2 through a plan-owned scratch buffer of batch * n elements
+ * (executions of such a plan must be ordered); other layout plans allocate
+ * only their twiddles.  UNSUPPORTED_SIZE otherwise, INVALID_ARG for a bad or
+ * self-overlapping layout.
  */
 fftc_status fftc_plan_layout(int64_t n, int64_t batch, int direction, int dtype, const fftc_layout *in,
                              const fftc_layout *out, fftc_plan_t *plan_out);

@@ -509,22 +509,56 @@ fftc_status fftc_plan_layout(int64_t n, int64_t batch, int direction, int dtype,
         if (dtype != FFTC_C64 && dtype != FFTC_C128)
             return fail(FFTC_ERR_INVALID_ARG, "layout plans take FFTC_C64 or FFTC_C128");
         if (batch < 1 || batch > (int64_t(1) << 40)) return fail(FFTC_ERR_INVALID_ARG, "batch must be in [1, 2^40]");
-        if (n < 2 || n > max_single_n(dtype) || !is_7smooth(n))
-            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "layout plans take single-kernel lengths 2 <= n <= " +
-                                                       std::to_string(max_single_n(dtype)) + " with prime factors <= 7");
+        if (n < 2 || n > max_total_n(dtype) || !is_7smooth(n))
+            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "layout plans take 2 <= n <= 2^20 with prime factors <= 7");
         const fftc_layout dflt{1, n, 0};
         const fftc_layout li = in ? *in : dflt, lo = out ? *out : dflt;
         fftc_status st = check_layout(li, n, batch, "in");
         if (st == FFTC_OK) st = check_layout(lo, n, batch, "out");
         if (st != FFTC_OK) return st;
-        std::vector<int> rs = choose_radices(n, dtype);
-        const SpecEntry* e = find_layout(dtype, n, rs);
-        if (!e) {
-            auto c = radix_candidates(n, 1);
-            if (!c.empty() && (e = find_layout(dtype, n, c[0])) != nullptr) rs = c[0];
+        // the single-kernel form (compiled with the layout accessors)
+        std::vector<int> rs;
+        const SpecEntry* e = nullptr;
+        if (n <= max_single_n(dtype)) {
+            rs = choose_radices(n, dtype);
+            if (!(e = find_layout(dtype, n, rs))) {
+                auto c = radix_candidates(n, 1);
+                if (!c.empty() && (e = find_layout(dtype, n, c[0])) != nullptr) rs = c[0];
+            }
         }
-        if (!e)
-            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no compiled layout kernel for n = " + std::to_string(n));
+        // a column-like side whose tile would hold fewer than 8 transforms (or
+        // a length without a single kernel): Eq. 2 in two passes of TC
+        // transforms each, with compiled column kernels for both factors
+        const bool cols = li.dist < li.stride || lo.dist < lo.stride;
+        const FourStepEntry *c1 = nullptr, *c2 = nullptr;
+        int64_t m = 0, k = 0;
+        std::vector<int> r1, r2;
+        if (cols && (!e || e->tile_tc < 8)) {
+            for (int64_t a = 2; a <= 1024; ++a) {  // most balanced split with both factors <= 1024
+                if (n % a || n / a > 1024 || n / a < 2) continue;
+                if (!m || std::llabs(a - n / a) < std::llabs(m - k)) {
+                    m = a;
+                    k = n / a;
+                }
+            }
+            auto pick = [&](int64_t len, const FourStepEntry** fs) {
+                std::vector<int> r = choose_radices(len, dtype);
+                if (!(*fs = find_colpass(dtype, len, r))) {
+                    auto c = radix_candidates(len, 1);
+                    if (!c.empty() && (*fs = find_colpass(dtype, len, c[0])) != nullptr) r = c[0];
+                }
+                return r;
+            };
+            if (m) {
+                r1 = pick(m, &c1);
+                r2 = pick(k, &c2);
+            }
+            if (!c1 || !c2) c1 = c2 = nullptr;
+        }
+        if (!e && !c1)
+            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no compiled layout kernel for n = " + std::to_string(n) +
+                                                       (cols ? "" : " (lengths above the single-kernel limit "
+                                                                    "take column-like layouts only)"));
         fftc_plan_s* p = new (std::nothrow) fftc_plan_s();
         if (!p) return fail(FFTC_ERR_OUT_OF_MEMORY, "host allocation failed");
         p->n = n;
@@ -532,17 +566,46 @@ fftc_status fftc_plan_layout(int64_t n, int64_t batch, int direction, int dtype,
         p->direction = direction;
         p->dtype = dtype;
         hipGetDevice(&p->device);
-        p->variant = FFTC_VARIANT_SINGLE_SPECIALISED;
-        p->radices = rs;
-        p->spec = e;
-        p->tpt = e->tpt;
-        p->t = e->t;
         p->has_layout = true;
         p->lin = li;
         p->lout = lo;
         std::vector<TwSegment> segs;
-        const int64_t entries = stage_segments(rs, 0, &segs);
+        int64_t entries = 0;
+        if (c1) {
+            p->variant = FFTC_VARIANT_TWO_PASS;
+            p->col1 = c1;
+            p->col2 = c2;
+            p->m = m;
+            p->k = k;
+            p->r1 = r1;
+            p->r2 = r2;
+            p->radices = r1;
+            p->radices.insert(p->radices.end(), r2.begin(), r2.end());
+            p->tpt = c1->tpt;
+            p->t = c1->tc;
+            p->tw1_off = 0;
+            entries += stage_segments(r1, entries, &segs);
+            p->tw2_off = entries;
+            entries += stage_segments(r2, entries, &segs);
+            p->twn_off = entries;
+            const int64_t nhi = (n + kTwSplit - 1) / kTwSplit;
+            segs.push_back({p->twn_off, kTwSplit, kTwSplit, n, 1});
+            segs.push_back({p->twn_off + kTwSplit, nhi, nhi, n, kTwSplit});
+            entries += kTwSplit + nhi;
+        } else {
+            p->variant = FFTC_VARIANT_SINGLE_SPECIALISED;
+            p->radices = rs;
+            p->spec = e;
+            p->tpt = e->tpt;
+            p->t = e->t;
+            entries = stage_segments(rs, 0, &segs);
+        }
         st = alloc_tables(p, segs, entries);
+        if (st == FFTC_OK && p->col1) {
+            p->scratch_bytes = (size_t)batch * (size_t)n * csize_of(dtype);
+            hipError_t he = hipMalloc(&p->scratch, p->scratch_bytes);
+            if (he != hipSuccess) st = fail_hip(he, "hipMalloc(column scratch)");
+        }
         if (st != FFTC_OK) {
             std::string keep = t_last_error;
             fftc_destroy_plan(p);

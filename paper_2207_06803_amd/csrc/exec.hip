@@ -196,9 +196,41 @@ static GAcc<Real> make_acc(const fftc_layout& l, const void* re, const void* im)
     return a;
 }
 
+template <typename Real>
+static fftc_status launch_layout_cols(const fftc_plan_s* p, const GAcc<Real>& a, const GAcc<Real>& b, int64_t batch,
+                                      hipStream_t s) {
+    const bool inv = p->direction == FFTC_INVERSE;
+    const cplx<Real>* tw = static_cast<const cplx<Real>*>(p->tw);
+    const cplx<Real>* tw1 = tw + p->tw1_off;
+    const cplx<Real>* tw2 = tw + p->tw2_off;
+    const cplx<Real>* twn = tw + p->twn_off;
+    cplx<Real>* scr = static_cast<cplx<Real>*>(p->scratch);
+    const FourStepEntry* f1 = p->col1;
+    const FourStepEntry* f2 = p->col2;
+    int k = (int)p->k, m = (int)p->m;
+    const int64_t g1 = (batch + f1->tc - 1) / f1->tc, g2 = (batch + f2->tc - 1) / f2->tc;
+    if (!grid_fits(g1) || !grid_fits(g2)) return fail(FFTC_ERR_INVALID_ARG, "batch too large for one launch");
+    GAcc<Real> aa = a, bb = b;
+    void* args1[] = {(void*)&aa, (void*)&bb, (void*)&scr, (void*)&tw1, (void*)&twn, (void*)&batch, (void*)&k};
+    hipError_t e = hipLaunchKernel(f1->fn[0][inv ? 1 : 0], dim3((unsigned)g1, (unsigned)k), dim3(f1->tpt * f1->tc),
+                                   args1, 0, s);
+    if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(col_two_pass 1)");
+    void* args2[] = {(void*)&aa, (void*)&bb, (void*)&scr, (void*)&tw2, (void*)&twn, (void*)&batch, (void*)&m};
+    e = hipLaunchKernel(f2->fn[1][inv ? 1 : 0], dim3((unsigned)g2, (unsigned)m), dim3(f2->tpt * f2->tc), args2, 0, s);
+    if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(col_two_pass 2)");
+    return FFTC_OK;
+}
+
 fftc_status launch_layout(const fftc_plan_s* p, const void* in_re, const void* in_im, void* out_re, void* out_im,
                           int64_t batch, hipStream_t s) {
     const bool inv = p->direction == FFTC_INVERSE;
+    if (p->col1) {
+        if (p->dtype == FFTC_C128)
+            return launch_layout_cols<double>(p, make_acc<double>(p->lin, in_re, in_im),
+                                              make_acc<double>(p->lout, out_re, out_im), batch, s);
+        return launch_layout_cols<float>(p, make_acc<float>(p->lin, in_re, in_im),
+                                         make_acc<float>(p->lout, out_re, out_im), batch, s);
+    }
     // column-like sides (dist < stride) go through the tile kernel
     int in_cols = p->lin.dist < p->lin.stride ? 1 : 0, out_cols = p->lout.dist < p->lout.stride ? 1 : 0;
     const bool tile = (in_cols || out_cols) && p->spec->tile_fwd;

@@ -80,6 +80,8 @@ struct FourStepEntry {
     const void* fn[2][2];  // [pass - 1][inverse]
 };
 const FourStepEntry* find_fourstep(int dtype, int64_t len, const std::vector<int>& rs);
+// Two-pass kernels for column-like layouts (layout_tile.h), same lengths.
+const FourStepEntry* find_colpass(int dtype, int64_t len, const std::vector<int>& rs);
 
 // Alternative orders (orders.h): N = radix^t in one LDS-resident kernel.
 struct OrderEntry {

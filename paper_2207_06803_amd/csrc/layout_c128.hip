@@ -15,4 +15,14 @@ const SpecEntry* layout_table_c128(int* count) {
     return k_table;
 }
 
+// two-pass column kernels: the column lengths of the two-pass plans
+#define C(N, ...) ColPassInst<double, 8, N, __VA_ARGS__>::entry(FFTC_C128),
+static const FourStepEntry k_cols[] = {FFTC_FOURSTEP_LIST_C128(C)};
+#undef C
+
+const FourStepEntry* colpass_table_c128(int* count) {
+    *count = (int)(sizeof(k_cols) / sizeof(k_cols[0]));
+    return k_cols;
+}
+
 }  // namespace fftc

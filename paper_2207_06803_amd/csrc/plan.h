@@ -40,6 +40,10 @@ struct fftc_plan_s {
     // layout plan: the compiled kernel with layout accessors, and the layouts
     bool has_layout = false;
     fftc_layout lin{}, lout{};
+    // column-like layouts beyond the tile kernel: two passes through `scratch`
+    // (m, k, r1, r2, tw1_off, tw2_off, twn_off as for two-pass plans)
+    const fftc::FourStepEntry* col1 = nullptr;
+    const fftc::FourStepEntry* col2 = nullptr;
     // order plan
     const fftc::OrderEntry* order = nullptr;
 };

@@ -51,6 +51,22 @@ const SpecEntry* find_layout(int dtype, int64_t n, const std::vector<int>& rs) {
 
 const FourStepEntry* fourstep_table_c64(int* count);
 const FourStepEntry* fourstep_table_c128(int* count);
+const FourStepEntry* colpass_table_c64(int* count);
+const FourStepEntry* colpass_table_c128(int* count);
+
+const FourStepEntry* find_colpass(int dtype, int64_t len, const std::vector<int>& rs) {
+    int cnt = 0;
+    const FourStepEntry* tab = dtype == FFTC_C128 ? colpass_table_c128(&cnt) : colpass_table_c64(&cnt);
+    for (int i = 0; i < cnt; ++i) {
+        const FourStepEntry& e = tab[i];
+        if (e.len != len || e.nr != (int)rs.size()) continue;
+        bool same = true;
+        for (int q = 0; q < e.nr; ++q) same = same && e.radices[q] == rs[q];
+        if (same) return &e;
+    }
+    return nullptr;
+}
+
 const OrderEntry* order_table_c64(int* count);
 const OrderEntry* order_table_c128(int* count);
 

@@ -146,6 +146,34 @@ def test_agrees_with_interleaved_plan_and_is_deterministic(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_two_pass_columns(dtype):
+    # column-like sides beyond the tile kernel: two passes through scratch
+    for n in (4096, 8192, 3 * 2048, 32768, 1 << 20) + ((16384,) if dtype == "c64" else ()):
+        b = 21 if n <= 32768 else 3
+        x = synth.uniform_complex(synth.rng(137, n), (b, n), np_dtype(dtype))
+        for lin, lout in [((b, 1, 0), (b, 1, 0)), ((b + 2, 1, 1), (1, n, 0)), ((1, n + 3, 1), (b, 1, 1))]:
+            for d in (FWD, INV):
+                say(f"two-pass columns n={n} {dtype} {lin}->{lout} dir={d}")
+                with fftc.plan_layout(n, b, d, dtype, lin, lout) as p:
+                    assert p.describe()["scratch_bytes"] == b * n * np.dtype(np_dtype(dtype)).itemsize
+                    y, clean = run_layout(p, x, lin, lout, dtype)
+                    if lin == lout:
+                        y_in, clean_in = run_layout(p, x, lin, lout, dtype, inplace=True)
+                        assert np.array_equal(y, y_in) and clean_in
+                if n <= 8192:
+                    assert rel_l2(y, oracle.dft(x, d)).max() <= tol_for(n, dtype), (n, lin, lout)
+                else:  # sampled outputs of sampled transforms (the O(n^2) oracle one output at a time)
+                    g = synth.rng(138, n)
+                    ks = np.unique(np.r_[0, 1, n // 3, n - 1, g.integers(0, n, 12)])
+                    for row in sorted({0, b // 2, b - 1}):
+                        ref = oracle.dft_points(x[row], ks, d)
+                        scale = np.sqrt(n * (np.abs(x[row].astype(np.complex128)) ** 2).sum())
+                        err = np.linalg.norm(y[row][ks] - ref) / (scale * np.sqrt(len(ks) / n))
+                        assert err <= tol_for(n, dtype), (n, row, err)
+                assert clean
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_columns_every_length(dtype):
     # the tile kernel of every compiled length, with a ragged last tile
     for n in layout_lengths(dtype):

@@ -35,8 +35,10 @@ def test_overlap_rule_edges():
 def test_unsupported():
     assert status(1, 1, "c64", None, None) == 2
     assert status(11, 1, "c64", None, None) == 2
-    assert status(1 << 15, 1, "c64", None, None) == 2
+    assert status(1 << 15, 1, "c64", None, None) == 2   # beyond one kernel: column-like layouts only
     assert status(16384, 1, "c128", None, None) == 2
+    assert status(1 << 21, 1, "c64", (1, 1 << 21, 0), (1, 1, 0)) == 2
+    assert status(11 * 1024, 4, "c64", (4, 1, 0), None) == 2  # a factor with a prime above 7
 
 
 def test_bad_dtype_and_execute():
