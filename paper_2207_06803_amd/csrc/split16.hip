@@ -105,10 +105,23 @@ template <int N> constexpr int split_waves() { return N <= 4096 ? (N / 256 < 4 ?
 
 __device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
 
-// Multiply (re, im) of element p by the twiddle it needs as an input of the
-// stage with radix R2 after NS2 (table segment at TW2): w_{NS2 R2}^{r k}.
+// The twiddle element p needs as an input of the stage with radix R2 after
+// NS2 (table segment at TW2): w_{NS2 R2}^{r k} (1 when r = 0 or NS2 = 1).
 template <int N, int R2, int NS2, int TW2>
-__device__ __forceinline__ void next_twiddle(int p, float& re, float& im, const float2* __restrict__ tw) {
+__device__ __forceinline__ float2 next_twiddle(int p, const float2* __restrict__ tw) {
+    if constexpr (NS2 > 1) {
+        constexpr int NR2 = N / R2;
+        const int r = p / NR2, j = p - r * NR2, k = j % NS2;
+        // r = 0 reads the table's first entry and discards it (no branch)
+        const float2 w = tw[TW2 + (r > 0 ? (r - 1) * NS2 + k : 0)];
+        return r > 0 ? w : make_float2(1.f, 0.f);
+    }
+    return make_float2(1.f, 0.f);
+}
+
+// The same factor applied in place, read only where r > 0.
+template <int N, int R2, int NS2, int TW2>
+__device__ __forceinline__ void apply_next_twiddle(int p, float& re, float& im, const float2* __restrict__ tw) {
     if constexpr (NS2 > 1) {
         constexpr int NR2 = N / R2;
         const int r = p / NR2, j = p - r * NR2, k = j % NS2;
@@ -155,6 +168,23 @@ __device__ __forceinline__ void mfma_stage(float* re, float* im, const float2* _
                 for (int i = 0; i < 8; ++i) b[gi][t][i] = parts[i][t];
         }
     }
+    // the next stage's twiddles for this lane's outputs, loaded before the
+    // products so their latency overlaps the matrix-core work (workgroups of
+    // up to 4 waves: with 16 waves the registers they take cost more)
+    constexpr bool PREFETCH = R2 > 0 && W <= 4;
+    float2 wn[PREFETCH ? GPW : 1][4];
+    if constexpr (PREFETCH) {
+#pragma unroll
+        for (int gi = 0; gi < GPW; ++gi) {
+            const int grp = wave + gi * W;
+            const int j = grp * 16 + n;
+            const int kk = j % NS, q = j / NS;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                wn[gi][c] = grp < G ? next_twiddle<N, R2, NS2, TW2>(q * NS * 16 + (4 * g4 + c) * NS + kk, tw)
+                                    : make_float2(1.f, 0.f);
+        }
+    }
     __syncthreads();
     const float inv1 = 1.f / T::SCALE, inv2 = inv1 * inv1;
 #pragma unroll
@@ -181,7 +211,14 @@ __device__ __forceinline__ void mfma_stage(float* re, float* im, const float2* _
                 if constexpr (T::TERMS >= 2) { vr += inv1 * yr1[c]; vi += inv1 * yi1[c]; }
                 if constexpr (T::TERMS >= 3) { vr += inv2 * yr2[c]; vi += inv2 * yi2[c]; }
                 const int p = q * NS * 16 + m * NS + kk;
-                if constexpr (R2 > 0) next_twiddle<N, R2, NS2, TW2>(p, vr, vi, tw);
+                if constexpr (PREFETCH) {
+                    const float2 w = wn[gi][c];
+                    const float a = vr, bb = vi;
+                    vr = a * w.x - bb * w.y;
+                    vi = a * w.y + bb * w.x;
+                } else if constexpr (R2 > 0) {
+                    apply_next_twiddle<N, R2, NS2, TW2>(p, vr, vi, tw);
+                }
                 re[spad(p)] = vr;
                 im[spad(p)] = vi;
             }
