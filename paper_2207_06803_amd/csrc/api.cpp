@@ -212,6 +212,8 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
             p->r1 = pick(m, &p->fs1);
             p->r2 = pick(k, &p->fs2);
             const int tc = two_pass_cols(dtype);
+            // columns per pass-1 tile (the compiled kernel's own width)
+            const int tc1 = p->fs1 ? p->fs1->tc : tc;
             int tpt1, tpt2, tdummy;
             launch_shape(m, p->r1, (int)cs, &tpt1, &tdummy);
             launch_shape(k, p->r2, (int)cs, &tpt2, &tdummy);
@@ -229,13 +231,15 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
                 const int64_t nhi = (n + kTwSplit - 1) / kTwSplit;
                 segs.push_back({p->twn_off, kTwSplit, kTwSplit, n, 1});
                 segs.push_back({p->twn_off + kTwSplit, nhi, nhi, n, kTwSplit});
+                // then w_N^{c p} at [c M + p] for the c < tc1 columns of a tile
+                segs.push_back({p->twn_off + kTwSplit + nhi, tc1 * m, m, n, 1, 0});
                 fill_gen_desc(m, p->r1, tpt1, tc, p->tw1_off, &p->pass1);
                 fill_gen_desc(k, p->r2, tpt2, tc, p->tw2_off, &p->pass2);
                 p->radices = p->r1;
                 p->radices.insert(p->radices.end(), p->r2.begin(), p->r2.end());
                 p->tpt = tpt1;
                 p->t = tc;
-                st = alloc_tables(p, segs, p->twn_off + kTwSplit + nhi);
+                st = alloc_tables(p, segs, p->twn_off + kTwSplit + nhi + tc1 * m);
             }
             if (st == FFTC_OK && !t_plan_no_scratch) {
                 p->scratch_bytes = (size_t)batch * (size_t)n * cs;

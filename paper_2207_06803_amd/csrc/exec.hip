@@ -74,14 +74,28 @@ four_step_pass(const cplx<Real>* src, cplx<Real>* dst, const cplx<Real>* __restr
     const int t = (int)threadIdx.x - tr * d.tpt;
     gen_transform<false, true>((const C*)nullptr, (C*)nullptr, lds + tr * ldl, tw, d, t, true, false, false);
     if (PASS == 1) {
-        // row-major store z[(col0 + c) M + p] * w_N^{(col0 + c) p}; (col0+c) p < N
+        // row-major store z[(col0 + c) M + p] * w_N^{(col0 + c) p}; (col0+c) p < N.
+        // When a thread's p is the same at every step, the factor is
+        // w_N^{col0 p} (once) times twc[c M + p] = w_N^{c p}.
+        const C* twc = twn + kTwSplit + (int)((n + kTwSplit - 1) / kTwSplit);
+        const bool fixed_p = nthr % len == 0;
+        C a = mk((Real)1, (Real)0);
+        if (fixed_p) {
+            const int e = col0 * ((int)threadIdx.x % len);
+            a = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
+        }
         for (int l = (int)threadIdx.x; l < tot; l += nthr) {
             const int c = udiv(l, len_mul, len);
             const int p = l - c * len;
             if (c < cols) {
                 const int i = col0 + c;
-                const int e = i * p;  // < N <= 2^20
-                const C w = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
+                C w;
+                if (fixed_p) {
+                    w = cmul(a, twc[c * len + p]);
+                } else {
+                    const int e = i * p;  // < N <= 2^20
+                    w = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
+                }
                 dst[base + (int64_t)i * len + p] = cmul(lds[c * ldl + lds_pad(p)], w);
             }
         }

@@ -45,17 +45,37 @@ fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C*
     spec_stages<K, 1, 0, true, false, false, Rs...>((const C*)nullptr, (C*)nullptr, lds + tr * LDSN, tw, t, true,
                                                      true);
     if constexpr (PASS == 1) {
-        // row-major store of column i = col0 + c: z[i M + p] w_N^{i p} (i p < N),
-        // the factor formed from the fine and coarse tables
+        // row-major store of column i = col0 + c: z[i M + p] w_N^{i p} (i p < N).
+        // w_N^{i p} = w_N^{col0 p} w_N^{c p}: the first from the fine and coarse
+        // tables once per p a thread stores, the second from the table
+        // twc[c M + p] = w_N^{c p} (c < TC) that follows them, read with
+        // consecutive lanes on consecutive p.
+        // (Lengths whose rows do not repeat per thread read both tables per
+        // element.)
+        constexpr bool REPEAT = NTH % LEN == 0 || LEN % NTH == 0;
+        constexpr int PP = !REPEAT ? 1 : NTH % LEN == 0 ? 1 : LEN / NTH;  // distinct p per thread
+        const C* twc = twn + kTwSplit + (int)((n + kTwSplit - 1) / kTwSplit);
+        C a[PP];
+        if constexpr (REPEAT) {
+#pragma unroll
+            for (int pp = 0; pp < PP; ++pp) {
+                const int e = col0 * ((tid % LEN) + pp * NTH);  // < N <= 2^20
+                a[pp] = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
+            }
+        }
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int l = tid + i * NTH;
             const int c = l / LEN, p = l % LEN;
             if (l < TOT && c < cols) {
-                const int col = col0 + c;
-                const int e = col * p;  // < N <= 2^20
-                const C w = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
-                dst[base + (int64_t)col * LEN + p] = cmul(lds[c * LDSN + lds_pad(p)], w);
+                C w;
+                if constexpr (REPEAT) {
+                    w = cmul(a[i % PP], twc[c * LEN + p]);
+                } else {
+                    const int e = (col0 + c) * p;
+                    w = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
+                }
+                dst[base + (int64_t)(col0 + c) * LEN + p] = cmul(lds[c * LDSN + lds_pad(p)], w);
             }
         }
     } else {
