@@ -10,6 +10,8 @@ so the 256 MB last-level cache cannot serve the reads.
 The same JSON line carries the other workloads as extras (each timed with
 HIP events on the stream its kernels run on):
   * a plain device copy over the same rotating buffers (for scale)
+  * the headline lengths and the copy at 2^22, 2^24 and 2^26 elements per
+    launch (the fill and drain cost of one launch)
   * 64-point complex64, 1024 transforms: time per launch
   * complex128 at the headline sizes
   * 10,000 mixed-length transforms: one persistent launch (hipGraph) vs the
@@ -69,6 +71,8 @@ def parse():
     ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
                     help="write profiles/hbm_traffic.json from FETCH_SIZE / WRITE_SIZE runs of the headline "
                          "and of --calibrate-copy, then exit")
+    ap.add_argument("--extras", default="",
+                    help="comma-separated names of the extra workloads to run (default: all)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=10000.0)
     return ap.parse_args()
@@ -334,6 +338,31 @@ def copy_ceiling(torch, synth, timer):
     torch.cuda.empty_cache()
     return {"workload": "torch copy_ of 2^24 complex64 over 4 rotating buffer pairs", "us": avg * 1e3,
             "gbs": 16.0 * ELEMS / (avg * 1e-3) / 1e9}
+
+
+def launch_size(torch, fftc, synth, timer):
+    """The headline kernels and a plain copy at 2^22, 2^24 and 2^26 complex64
+    elements per launch (rotating buffers totalling >= 1 GiB): how much of a
+    2^24-element launch goes to filling and draining the GPU."""
+    out = {}
+    for lg in (22, 24, 26):
+        e = 1 << lg
+        nb = max(2, min(8, (1 << 30) // (8 * e)))
+        x0 = torch.from_numpy(synth.uniform_complex(synth.rng(7, lg), (e,), np.complex64)).to("cuda")
+        xs = [x0.clone() for _ in range(nb)]  # distinct buffers, the same values
+        ys = [torch.empty_like(x0) for _ in range(nb)]
+        del x0
+        row = {"buffers": nb}
+        for n in SIZES:
+            with fftc.Plan(n, e // n, fftc.FORWARD, "c64") as p:
+                ms = timer.avg_ms(lambda i: p.execute(xs[i % nb], ys[i % nb]), 20)
+            row[f"c64_{n}_fwd"] = {"us": ms * 1e3, "hbm_gbs": 16.0 * e / (ms * 1e-3) / 1e9}
+        ms = timer.avg_ms(lambda i: ys[i % nb].copy_(xs[i % nb]), 20)
+        row["torch_copy"] = {"us": ms * 1e3, "hbm_gbs": 16.0 * e / (ms * 1e-3) / 1e9}
+        out[f"2^{lg}"] = row
+        del xs, ys
+        torch.cuda.empty_cache()
+    return {"workload": "complex64 forward, 2^22 / 2^24 / 2^26 elements per launch", "by_elements": out}
 
 
 def formula(torch, fftc, synth, timer):
@@ -639,6 +668,7 @@ def main():
     extras = {}
     if not args.only_headline:
         for name, fn in (("copy_ceiling", lambda: copy_ceiling(torch, synth, timer)),
+                         ("launch_size", lambda: launch_size(torch, fftc, synth, timer)),
                          ("config1_n64", lambda: config1(torch, fftc, synth, timer)),
                          ("c128", lambda: c128(torch, fftc, synth, timer)),
                          ("two_pass", lambda: two_pass(torch, fftc, synth, timer)),
@@ -652,6 +682,8 @@ def main():
                          ("serving_4x_rate", lambda: config5(args, torch, fftc, synth, rate=4 * args.serve_rate)),
                          ("serving_4x_rate_unfused",
                           lambda: config5(args, torch, fftc, synth, fuse=False, rate=4 * args.serve_rate))):
+            if args.extras and name not in args.extras.split(","):
+                continue
             log(f"{name} ...")
             extras[name] = fn()
     cpu = None
