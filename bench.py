@@ -78,6 +78,30 @@ def parse():
     return ap.parse_args()
 
 
+def system_info(torch):
+    """GPU architecture, ROCm and torch versions, host CPU model and core count."""
+    info = {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None)}
+    try:
+        props = torch.cuda.get_device_properties(0)
+        info.update({"gpu": props.name, "gfx": getattr(props, "gcnArchName", None),
+                     "compute_units": props.multi_processor_count,
+                     "hbm_gib": round(props.total_memory / 2 ** 30, 1)})
+    except Exception:  # pragma: no cover - no device
+        pass
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            info["rocm"] = f.read().strip()
+    except OSError:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            info["cpu_model"] = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    info["host_cores"] = len(os.sched_getaffinity(0))
+    return info
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -175,10 +199,21 @@ def headline(args, torch, fftc, synth, timer):
     per = {}
     for p in plans:
         avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % NBUF], ys[i % NBUF], s), 20)
+        # per-launch distribution: 10 warm-up launches, then 100 between event pairs
+        for i in range(10):
+            p.execute(xs[i % NBUF], ys[i % NBUF], s)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+        for i, (a, b) in enumerate(ev):
+            a.record(s)
+            p.execute(xs[i % NBUF], ys[i % NBUF], s)
+            b.record(s)
+        torch.cuda.synchronize()
+        each = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
         d = p.describe()
         per[f"c64_{p.n}_{'fwd' if p.direction < 0 else 'inv'}"] = {
             "us": avg * 1e3, "gflops": flops(p.n, p.batch) / (avg * 1e-3) / 1e9,
             "hbm_gbs": 16.0 * p.n * p.batch / (avg * 1e-3) / 1e9,
+            "us_p10_median_p90": [float(np.percentile(each, q)) for q in (10, 50, 90)],
             "radices": d["radices"], "variant": d["variant"]}
     for p in plans:
         p.close()
@@ -686,6 +721,8 @@ def main():
                 continue
             log(f"{name} ...")
             extras[name] = fn()
+    if "copy_ceiling" in extras:
+        roofline["frac_of_copy"] = roofline["achieved"] / extras["copy_ceiling"]["gbs"]
     cpu = None
     if not args.no_cpu_baseline and not args.only_headline:
         log("cpu baseline ...")
@@ -710,6 +747,7 @@ def main():
         "per_kernel": h["per_kernel"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "system": system_info(torch),
         "extras": extras,
     }
     print(json.dumps(out), flush=True)
