@@ -576,20 +576,31 @@ def cpu_baseline(seconds):
         oracle.dft(x, -1)
         per[n] = (time.perf_counter() - t0) / threads
     budget = seconds / (2 * len(SIZES))
-    tot_flops, tot_t, counts = 0.0, 0.0, {}
+    tot_flops, tot_t, counts, rate = 0.0, 0.0, {}, {}
     for n in SIZES:
         cnt = max(threads, int(budget / per[n]) // threads * threads)
         counts[n] = cnt
         x = synth.uniform_complex(g, (cnt, n), np.complex64)
+        t_n = 0.0
         for sign in (-1, 1):
             t0 = time.perf_counter()
             oracle.dft(x, sign)
-            tot_t += time.perf_counter() - t0
+            t_n += time.perf_counter() - t0
             tot_flops += flops(n, cnt)
+        tot_t += t_n
+        rate[n] = 2 * cnt / t_n
+    # one core: a fixed subset of 64 forward transforms of N = 1024
+    x = synth.uniform_complex(g, (64, 1024), np.complex64)
+    t0 = time.perf_counter()
+    oracle.dft(x, -1, threads=1)
+    t1 = time.perf_counter() - t0
     return {"value": tot_flops / tot_t / 1e9, "unit": "GFLOP/s (5 N log2 N)", "cores": threads,
             "kind": "oracle",
             "sample": "FP64 O(N^2) oracle on complex64 inputs, forward+inverse, transforms per N: "
-                      + ", ".join(f"{n}:{c}" for n, c in counts.items()) + f" ({tot_t:.1f} s)"}
+                      + ", ".join(f"{n}:{c}" for n, c in counts.items()) + f" ({tot_t:.1f} s)",
+            "transforms_per_s": {str(n): r for n, r in rate.items()},
+            "one_core": {"sample": "64 forward transforms of N = 1024", "transforms_per_s": 64 / t1,
+                         "gflops": flops(1024, 64) / t1 / 1e9}}
 
 
 def rocpd_summary(paths):
