@@ -20,7 +20,7 @@ HIP events on the stream its kernels run on):
     error against the complex128 GPU path
   * serving: 20,000 Poisson-arriving requests, p50/p99 latency, with and
     without fusing same-length requests into one launch, at the configured
-    rate and at four times it
+    rate and at four times it, and a sweep of the arrival rate (1x to 32x)
   * formula plans (the Kronecker-product DSL): Eq. 2 programs folded onto
     the Stockham plans vs run as written, and 2-D DFT formulas
   * planar and strided layouts: planar in/out, planar in -> interleaved out,
@@ -32,6 +32,7 @@ and the FP64 oracle timed on the host cores as the CPU baseline.
 Prints one JSON line.  `value` is GFLOP/s in the 5 N log2 N convention.
 """
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -75,6 +76,7 @@ def parse():
                     help="comma-separated names of the extra workloads to run (default: all)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=10000.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
     return ap.parse_args()
 
 
@@ -494,16 +496,17 @@ def orders(torch, fftc, synth, timer):
             "by_n": out}
 
 
-def config5(args, torch, fftc, synth, fuse=True, rate=None):
+def config5(args, torch, fftc, synth, fuse=True, rate=None, nreq=None):
     from paper_2207_06803_amd import server as srv
     rate = rate or args.serve_rate
+    nreq = nreq or args.serve_requests
     g = synth.rng(5)
-    reqs = synth.serving_requests(synth.rng(5, 99), args.serve_requests, rate)
+    reqs = synth.serving_requests(synth.rng(5, 99), nreq, rate)
     pool_elems = (1 << 24) + (1 << 20)
     pool = torch.from_numpy(synth.uniform_complex(g, (pool_elems,), np.complex64)).to("cuda")
-    offs = g.integers(0, (1 << 20), size=args.serve_requests)
+    offs = g.integers(0, (1 << 20), size=nreq)
     budget = 64 << 30
-    srv.start(budget, n_streams=4, max_inflight=64, fuse=fuse)
+    srv.start(budget, n_streams=args.serve_streams, max_inflight=64, fuse=fuse)
     try:
         for n in sorted(set(int(v) for v in reqs["n"])):
             for d in (fftc.FORWARD, fftc.INVERSE):
@@ -512,6 +515,17 @@ def config5(args, torch, fftc, synth, fuse=True, rate=None):
         base = pool.data_ptr()
 
         def serve(N, tag0=0):
+            # the client loop runs without Python's cyclic collector: a pass of
+            # it over this process's objects would stall submissions for
+            # milliseconds and show up as queueing time
+            gc.collect()
+            gc.disable()
+            try:
+                return serve_run(N, tag0)
+            finally:
+                gc.enable()
+
+        def serve_run(N, tag0):
             t0 = srv.now_ns() + 2_000_000
             sched = t0 + (reqs["arrival_s"][:N] * 1e9).astype(np.int64)
             done = {}
@@ -536,9 +550,9 @@ def config5(args, torch, fftc, synth, fuse=True, rate=None):
             return sched, done
 
         # untimed warm-up on the first tenth of the stream (clocks, caches)
-        serve(max(1, args.serve_requests // 10), tag0=1 << 40)
+        serve(max(1, nreq // 10), tag0=1 << 40)
         st0 = srv.stats()
-        N = args.serve_requests
+        N = nreq
         sched, done = serve(N)
         st = srv.stats()
     finally:
@@ -560,6 +574,18 @@ def config5(args, torch, fftc, synth, fuse=True, rate=None):
             "sustained_gflops": fl / span / 1e9, "sustained_hbm_gbs": by / span / 1e9,
             "span_s": span, "offered_gbs": by / (reqs["arrival_s"][-1] + 1e-9) / 1e9,
             "peak_budget_bytes": st["peak_bytes"], "max_inflight_seen": st["max_inflight_seen"]}
+
+
+def serving_sweep(args, torch, fftc, synth):
+    """Latency against offered load: 10,000 requests per arrival rate, fused
+    admission, from the configured rate up to past what the GPU sustains."""
+    out = {}
+    for mult in (1, 2, 4, 8, 16, 32):
+        r = config5(args, torch, fftc, synth, rate=mult * args.serve_rate, nreq=10000)
+        out[f"{mult * args.serve_rate:.0f}"] = {k: r[k] for k in ("p50_us", "p99_us", "queue_p99_us",
+                                                                  "sustained_hbm_gbs", "offered_gbs")}
+    return {"workload": "10000 complex64 requests per rate, the serving mix, fused admission",
+            "fixed_rate_per_s": args.serve_rate, "by_rate_per_s": out}
 
 
 def cpu_baseline(seconds):
@@ -727,7 +753,8 @@ def main():
                          ("config5_serving_unfused", lambda: config5(args, torch, fftc, synth, fuse=False)),
                          ("serving_4x_rate", lambda: config5(args, torch, fftc, synth, rate=4 * args.serve_rate)),
                          ("serving_4x_rate_unfused",
-                          lambda: config5(args, torch, fftc, synth, fuse=False, rate=4 * args.serve_rate))):
+                          lambda: config5(args, torch, fftc, synth, fuse=False, rate=4 * args.serve_rate)),
+                         ("serving_sweep", lambda: serving_sweep(args, torch, fftc, synth))):
             if args.extras and name not in args.extras.split(","):
                 continue
             log(f"{name} ...")

@@ -113,6 +113,7 @@ struct InFlight {
     int64_t admit_ns, start_ns, mock_done_ns;
     hipEvent_t ev;
     fftc_status status;
+    int stream;  // index of the stream it was launched on (-1: none)
 };
 
 size_t elem_bytes(int dtype) { return dtype == FFTC_C128 ? 16 : 8; }
@@ -311,10 +312,12 @@ class Server {
             fftc_status st = get_plan(f.q.r.n, f.q.r.direction, f.q.r.dtype, f.q.r.batch, &p);
             if (st != FFTC_OK) return st;
         }
-        hipStream_t s = streams_[next_stream_];
+        const int si = next_stream_;
+        hipStream_t s = streams_[si];
         next_stream_ = (next_stream_ + 1) % (int)streams_.size();
         fftc_status st = fftc_execute_batch(p, f.q.r.in, f.out, f.q.r.batch, s);
         if (st != FFTC_OK) return st;
+        f.stream = si;
         f.ev = events_[slot];
         hipError_t e = hipEventRecord(f.ev, s);
         if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
@@ -350,7 +353,8 @@ class Server {
                 groups += (f.q.r.batch + e->t - 1) / e->t;
             }
             l.gstart[l.count] = groups;
-            hipStream_t s = streams_[next_stream_];
+            const int si = next_stream_;
+            hipStream_t s = streams_[si];
             next_stream_ = (next_stream_ + 1) % (int)streams_.size();
             const int64_t t0 = now_ns();
             fftc_status st = launch_reqs(e, r0.direction == FFTC_INVERSE, l, groups, p->tw, s);
@@ -361,6 +365,7 @@ class Server {
                 f.status = st;
                 if (st != FFTC_OK) continue;
                 f.ev = events_[grp[i]->second];
+                f.stream = si;
                 hipError_t err = hipEventRecord(f.ev, s);
                 if (err != hipSuccess) f.status = fail_hip(err, "hipEventRecord");
             }
@@ -398,7 +403,16 @@ class Server {
         if (!mock_) (void)hipSetDevice(device_);
         std::vector<int> free_slots;
         for (int i = cfg_.max_inflight - 1; i >= 0; --i) free_slots.push_back(i);
-        std::vector<std::pair<InFlight, int>> running;
+        // running work: per stream in launch order (a stream completes its
+        // work in order, so only the oldest entry of each needs an event
+        // query); the mock executor's work and failed launches in `other`
+        std::vector<std::deque<std::pair<InFlight, int>>> by_stream(std::max<size_t>(streams_.size(), 1));
+        std::vector<std::pair<InFlight, int>> other;
+        auto n_running = [&]() {
+            size_t k = other.size();
+            for (auto& q : by_stream) k += q.size();
+            return k;
+        };
         for (;;) {
             bool progressed = false;
             std::vector<std::pair<InFlight, int>> to_launch;
@@ -428,6 +442,7 @@ class Server {
                     size_t off = 0;
                     if (!arena_.alloc(pending_.front().bytes, &off)) break;
                     InFlight f{};
+                    f.stream = -1;
                     f.q = pending_.front();
                     pending_.pop_front();
                     f.off = off;
@@ -439,36 +454,48 @@ class Server {
                     free_slots.pop_back();
                     ++stats_.admitted;
                 }
-                running_count_ = (int)(running.size() + to_launch.size());
+                running_count_ = (int)(n_running() + to_launch.size());
                 stats_.max_inflight_seen = std::max<int>(stats_.max_inflight_seen, running_count_);
             }
             launch_round(to_launch);
             for (auto& fl : to_launch) {
-                running.push_back(fl);
+                if (!mock_ && fl.first.status == FFTC_OK && fl.first.stream >= 0)
+                    by_stream[fl.first.stream].push_back(fl);
+                else
+                    other.push_back(fl);
                 progressed = true;
             }
             // completions
             std::vector<fftc_completion> fin;
             std::vector<void*> failed_out;
-            for (size_t i = 0; i < running.size();) {
-                if (finished(running[i].first)) {
-                    InFlight& f = running[i].first;
-                    fftc_completion c{};
-                    c.tag = f.q.r.tag;
-                    c.status = f.status;
-                    c.out = f.status == FFTC_OK ? f.out : nullptr;
-                    c.arrival_ns = f.q.r.arrival_ns;
-                    c.admit_ns = f.admit_ns;
-                    c.start_ns = f.start_ns;
-                    c.done_ns = now_ns();
-                    c.n = f.q.r.n;
-                    c.batch = f.q.r.batch;
-                    if (f.status != FFTC_OK) failed_out.push_back(f.out);
-                    fin.push_back(c);
-                    free_slots.push_back(running[i].second);
-                    running[i] = running.back();
-                    running.pop_back();
-                    progressed = true;
+            auto complete = [&](std::pair<InFlight, int>& r) {
+                InFlight& f = r.first;
+                fftc_completion c{};
+                c.tag = f.q.r.tag;
+                c.status = f.status;
+                c.out = f.status == FFTC_OK ? f.out : nullptr;
+                c.arrival_ns = f.q.r.arrival_ns;
+                c.admit_ns = f.admit_ns;
+                c.start_ns = f.start_ns;
+                c.done_ns = now_ns();
+                c.n = f.q.r.n;
+                c.batch = f.q.r.batch;
+                if (f.status != FFTC_OK) failed_out.push_back(f.out);
+                fin.push_back(c);
+                free_slots.push_back(r.second);
+                progressed = true;
+            };
+            for (auto& q : by_stream) {
+                while (!q.empty() && finished(q.front().first)) {
+                    complete(q.front());
+                    q.pop_front();
+                }
+            }
+            for (size_t i = 0; i < other.size();) {
+                if (finished(other[i].first)) {
+                    complete(other[i]);
+                    other[i] = other.back();
+                    other.pop_back();
                 } else {
                     ++i;
                 }
@@ -487,14 +514,15 @@ class Server {
                     ++stats_.completed;
                     if (c.status != FFTC_OK) ++stats_.failed;
                 }
-                running_count_ = (int)running.size();
-                if (stop_ && running.empty() && incoming_.empty() && pending_.empty()) break;
+                const size_t nrun = n_running();
+                running_count_ = (int)nrun;
+                if (stop_ && nrun == 0 && incoming_.empty() && pending_.empty()) break;
                 // idle, or the queue head waits for memory or a slot: sleep
                 // until a submit, release or stop (or a short timeout)
-                if (!progressed && running.empty()) cv_.wait_for(lk, std::chrono::milliseconds(2));
+                if (!progressed && nrun == 0) cv_.wait_for(lk, std::chrono::milliseconds(2));
             }
             // work on the GPU: poll its events without a timed sleep
-            if (!progressed && !running.empty()) std::this_thread::yield();
+            if (!progressed && n_running() > 0) std::this_thread::yield();
         }
     }
 
