@@ -1,9 +1,10 @@
 // The persistent mixed-length kernel (instantiated per element type in
 // mixed_c64.hip / mixed_c128.hip, which supply the list of compiled bodies).
 //
-// Each resident workgroup loops: take the next item index from the atomic
-// counter (counter[0]), leave when it is past the end, otherwise run the
-// item's transforms with its class's body -- a compiled Stockham list when one
+// Each resident workgroup loops over items: its first is its own index, each
+// later one comes from the atomic counter (counter[0], offset by the grid
+// size); it leaves when the item is past the end, otherwise runs the item's
+// transforms with its class's body -- a compiled Stockham list when one
 // exists, else the runtime-radix stages.  Threads beyond the class's
 // transforms only take part in the barriers.  Every workgroup counts its exit
 // in counter[1]; the last one resets both counters, so consecutive launches
@@ -31,11 +32,11 @@ extern "C" __shared__ __align__(16) unsigned char fftc_dyn_lds[];
         using C = cplx<Real>;                                                                        \
         C* lds = reinterpret_cast<C*>(fftc_dyn_lds);                                                 \
         __shared__ int s_item;                                                                       \
+        /* the first item is the workgroup's own index (the grid never exceeds \
+           the item count); later ones come from the counter, requested at the \
+           start of an item and read after it, so the atomic's latency hides */ \
+        int it = (int)blockIdx.x;                                                                    \
         for (;;) {                                                                                   \
-            if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);                              \
-            __syncthreads();                                                                         \
-            const int it = s_item;                                                                   \
-            __syncthreads();                                                                         \
             if (it >= nitems) {                                                                      \
                 /* the last workgroup out clears both counters for the next launch */               \
                 if (threadIdx.x == 0 && atomicAdd(counter + 1, 1u) == gridDim.x - 1) {               \
@@ -44,6 +45,8 @@ extern "C" __shared__ __align__(16) unsigned char fftc_dyn_lds[];
                 }                                                                                    \
                 break;                                                                               \
             }                                                                                        \
+            unsigned int nx = 0;                                                                     \
+            if (threadIdx.x == 0) nx = gridDim.x + atomicAdd(counter, 1u);                           \
             const MixedItem item = items[it];                                                        \
             const MixedClass& c = classes[item.cls];                                                 \
             const GenDesc& d = c.desc;                                                               \
@@ -55,9 +58,7 @@ extern "C" __shared__ __align__(16) unsigned char fftc_dyn_lds[];
             C* ldsp = lds + (member ? tr : 0) * c.ldsn;                                              \
             if (d.nst == 0) {                                                                        \
                 if (valid && t == 0) out[toff] = in[toff];                                           \
-                continue;                                                                            \
-            }                                                                                        \
-            if (c.body >= 0) {                                                                       \
+            } else if (c.body >= 0) {                                                                \
                 const C* twc = tw + c.twbase;                                                        \
                 switch (c.body) {                                                                    \
                     LIST(FFTC_BODY_CASE)                                                             \
@@ -66,6 +67,10 @@ extern "C" __shared__ __align__(16) unsigned char fftc_dyn_lds[];
             } else {                                                                                 \
                 gen_transform<INV, true>(in + toff, out + toff, ldsp, tw, d, t, valid);              \
             }                                                                                        \
+            if (threadIdx.x == 0) s_item = (int)nx;                                                  \
+            __syncthreads();                                                                         \
+            it = s_item;                                                                             \
+            __syncthreads();                                                                         \
         }                                                                                            \
     }
 
