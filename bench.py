@@ -710,8 +710,8 @@ def main():
         traffic_json(*args.traffic_json)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
-                                   "this build (--gpus must be 1)", "n_gpus": args.gpus}), flush=True)
+        print(json.dumps({"error": "this benchmark runs on one GPU: the library has no multi-GPU path "
+                                   "(--gpus must be 1)", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import torch
     from paper_2207_06803_amd import fftc, synth
