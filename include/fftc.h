@@ -306,10 +306,14 @@ fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int *ra
  *                     (the product of the recursion's Pi factors), then t
  *                     in-place radix-R stages (decimation in time);
  *   FFTC_ORDER_PEASE  constant geometry: every stage reads x[j + r N/R] and
- *                     writes y[j R + r]; explicit digit reversal on output.
+ *                     writes y[j R + r]; explicit digit reversal on output;
+ *   FFTC_ORDER_FOURSTEP  Eq. 2 applied once (the block form): N = K M with
+ *                     M = R^ceil(t/2), K = R^floor(t/2); Pi^N_K on load, DFT_M
+ *                     on the K rows, D^N_M, DFT_K on the M columns (radix-R
+ *                     Stockham stages for both), natural-order store.
  * Same conventions and results as fftc_plan (up to rounding).
  * ------------------------------------------------------------------------- */
-enum { FFTC_ORDER_STOCKHAM = 0, FFTC_ORDER_CT = 1, FFTC_ORDER_PEASE = 2 };
+enum { FFTC_ORDER_STOCKHAM = 0, FFTC_ORDER_CT = 1, FFTC_ORDER_PEASE = 2, FFTC_ORDER_FOURSTEP = 3 };
 
 fftc_status fftc_plan_order(int64_t n, int64_t batch, int direction, int dtype, int order, int radix,
                             fftc_plan_t *plan_out);

@@ -19,6 +19,13 @@
 //    digit-reversed order, and the explicit reversal is the store's read
 //    address.  (Derived from the Stockham stages by conjugating each with the
 //    digit permutation that makes its addressing constant.)
+//  ORDER_FOURSTEP (Eq. 2 applied once, the block form): N = K M with
+//    M = R^ceil(t/2), K = R^floor(t/2).  The load applies Pi^N_K (element
+//    x[j K + i] goes to row i, column j of a K x M array); the K rows are
+//    transformed by DFT_M (Stockham stages of radix R on each contiguous
+//    row); the first stage of the column transforms multiplies element
+//    (i, p) by w_N^{i p} (D^N_M); the M columns (stride M) are transformed by
+//    DFT_K, which leaves y[q M + p] in natural order.
 //
 // Twiddles come from one table of w_N^e, e < N (w_L^a = w_N^{a N / L}).
 #pragma once
@@ -28,9 +35,10 @@
 
 namespace fftc {
 
-enum { ORDER_STOCKHAM = 0, ORDER_CT = 1, ORDER_PEASE = 2 };
+enum { ORDER_STOCKHAM = 0, ORDER_CT = 1, ORDER_PEASE = 2, ORDER_FOURSTEP = 3 };
 
 constexpr int ilog(int n, int r) { return n <= 1 ? 0 : 1 + ilog(n / r, r); }
+constexpr int ipow(int r, int e) { return e == 0 ? 1 : r * ipow(r, e - 1); }
 
 // reversal of the D low base-R digits of e
 template <int R, int D> __device__ __forceinline__ int drev(int e) {
@@ -50,7 +58,9 @@ order_kernel(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __restrict
     constexpr int TS = ilog(N, R);  // stages
     constexpr int NR = N / R, BPT = NR / TPT, NTH = TPT * T;
     constexpr int LDSN = lds_len(N);
-    constexpr int NBUF = ORDER == ORDER_PEASE ? 2 : 1;
+    constexpr int NBUF = ORDER == ORDER_CT ? 1 : 2;
+    // four-step split: rows of M = R^TM, columns of K = R^TK
+    constexpr int TK = TS / 2, TM = TS - TK, M = ipow(R, TM), K = ipow(R, TK);
     static_assert(NR % TPT == 0, "butterflies must split evenly");
     __shared__ C lds[NBUF * T * LDSN];
     const int tid = (int)threadIdx.x;
@@ -72,7 +82,10 @@ order_kernel(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __restrict
         const int l = tid + i * NTH;
         if (l < TOT) {
             const int e = l % N;
-            lds[(l / N) * LDSN + lds_pad(ORDER == ORDER_CT ? drev<R, TS>(e) : e)] = buf[i];
+            const int dst = ORDER == ORDER_CT         ? drev<R, TS>(e)
+                            : ORDER == ORDER_FOURSTEP ? (e % K) * M + e / K  // Pi^N_K
+                                                      : e;
+            lds[(l / N) * LDSN + lds_pad(dst)] = buf[i];
         }
     }
     __syncthreads();
@@ -101,6 +114,57 @@ order_kernel(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __restrict
                 for (int r = 0; r < R; ++r) a[lds_pad(base + r * m)] = v[r];
             }
             __syncthreads();
+        } else if constexpr (ORDER == ORDER_FOURSTEP) {
+            if (s < TM) {
+                // DFT_M on each contiguous row, Stockham stage s (ns = m)
+                constexpr int MR = M / R;
+#pragma unroll
+                for (int i = 0; i < BPT; ++i) {
+                    const int bf = t + i * TPT;
+                    const int row = bf / MR, j = bf - row * MR;
+                    const int k = j % m;
+                    C v[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[r] = a[lds_pad(row * M + j + r * MR)];
+                    if (s > 0) {
+#pragma unroll
+                        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twn[r * k * (N / (m * R))]);
+                    }
+                    Codelet<R, C>::run(v);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) b[lds_pad(row * M + (j / m) * m * R + r * m + k)] = v[r];
+                }
+            } else {
+                // DFT_K on each column (stride M), Stockham stage s - TM; its
+                // first stage also applies D^N_M
+                constexpr int KR = K / R;
+                int ns = 1;
+#pragma unroll
+                for (int u = TM; u < s; ++u) ns *= R;
+#pragma unroll
+                for (int i = 0; i < BPT; ++i) {
+                    const int bf = t + i * TPT;
+                    const int j = bf / M, p = bf - j * M;
+                    const int k = j % ns;
+                    C v[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[r] = a[lds_pad((j + r * KR) * M + p)];
+                    if (s == TM) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) v[r] = cmul(v[r], twn[(j + r * KR) * p]);  // < K M = N
+                    } else {
+#pragma unroll
+                        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twn[r * k * (N / (ns * R))]);
+                    }
+                    Codelet<R, C>::run(v);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) b[lds_pad(((j / ns) * ns * R + r * ns + k) * M + p)] = v[r];
+                }
+            }
+            __syncthreads();
+            C* tmp = a;
+            a = b;
+            b = tmp;
         } else {
 #pragma unroll
             for (int i = 0; i < BPT; ++i) {
@@ -131,7 +195,7 @@ order_kernel(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __restrict
         const int l = tid + i * NTH;
         const int q = l / N, e = l % N;
         if (l < TOT && q < count) {
-            C* src = (ORDER == ORDER_PEASE && (TS % 2 == 1)) ? lds + (T + q) * LDSN : lds + q * LDSN;
+            C* src = (ORDER != ORDER_CT && (TS % 2 == 1)) ? lds + (T + q) * LDSN : lds + q * LDSN;
             st_out<INV>(out + (b0 + q) * N + e, src[lds_pad(ORDER == ORDER_PEASE ? drev<R, TS>(e) : e)]);
         }
     }
@@ -142,7 +206,7 @@ struct OrderInst {
     static constexpr int BPT0 = kMaxElemsPerThread / R >= 1 ? kMaxElemsPerThread / R : 1;
     static constexpr int TPT0 = (N / R) / BPT0 >= 1 ? (N / R) / BPT0 : 1;
     static constexpr int TPT = TPT0 > 1024 ? 1024 : TPT0;
-    static constexpr int NBUF = ORDER == ORDER_PEASE ? 2 : 1;
+    static constexpr int NBUF = ORDER == ORDER_CT ? 1 : 2;
     static constexpr int CS = (int)sizeof(cplx<Real>);
     static constexpr int T0 = TPT >= 256 ? 1 : 256 / TPT;
     static constexpr int T = (T0 * NBUF * lds_len(N) * CS > kLdsMaxPerGroup) ? 1 : T0;

@@ -134,7 +134,7 @@ std::vector<int> choose_radices(int64_t n, int dtype) {
 
 // ---- tuning database ----------------------------------------------------------
 // Text file, one line per entry:  <arch> <c64|c128> <n> [<order>:]<r1,r2,...> <ms>
-// with <order> "ct" or "pease" for an alternative order (its list is the
+// with <order> "ct", "pease" or "fourstep" for an alternative order (its list is the
 // radix repeated), none for Stockham.  Entries for another architecture are
 // ignored; a list that does not multiply to n is ignored.
 namespace {
@@ -162,7 +162,7 @@ int load_locked(const char* path) {
         char* list = rl;
         if (char* colon = strchr(rl, ':')) {
             *colon = 0;
-            order = strcmp(rl, "ct") == 0 ? 1 : strcmp(rl, "pease") == 0 ? 2 : -1;
+            order = strcmp(rl, "ct") == 0 ? 1 : strcmp(rl, "pease") == 0 ? 2 : strcmp(rl, "fourstep") == 0 ? 3 : -1;
             list = colon + 1;
         }
         if (order < 0) continue;
@@ -242,7 +242,8 @@ int tune_save_file(const char* path) {
     for (auto& kv : g_tune) {
         fprintf(f, "%s %s %lld ", kTuneArch, kv.first.second == FFTC_C128 ? "c128" : "c64",
                 (long long)kv.first.first);
-        if (kv.second.order) fprintf(f, "%s:", kv.second.order == 1 ? "ct" : "pease");
+        if (kv.second.order)
+            fprintf(f, "%s:", kv.second.order == 1 ? "ct" : kv.second.order == 2 ? "pease" : "fourstep");
         const auto& rs = kv.second.rs;
         for (size_t i = 0; i < rs.size(); ++i) fprintf(f, i ? ",%d" : "%d", rs[i]);
         fprintf(f, " %.6f\n", kv.second.ms);

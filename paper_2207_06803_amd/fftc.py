@@ -35,7 +35,8 @@ VARIANT_NAMES = {0: "single_specialised", 1: "single_generic", 2: "two_pass", 3:
 ORDER_STOCKHAM = 0
 ORDER_CT = 1
 ORDER_PEASE = 2
-ORDER_NAMES = {0: "stockham", 1: "ct", 2: "pease"}
+ORDER_FOURSTEP = 3
+ORDER_NAMES = {0: "stockham", 1: "ct", 2: "pease", 3: "fourstep"}
 
 # formula plan flags
 FORMULA_NO_FOLD = 1
@@ -329,7 +330,7 @@ def execute_layout(plan: Plan, in_re, in_im, out_re, out_im, stream=None) -> Non
 
 
 def plan_order(n: int, batch: int, direction: int = FORWARD, dtype="c64", order=ORDER_CT, radix: int = 2) -> Plan:
-    """Plan running an alternative factorisation order (ORDER_CT / ORDER_PEASE)."""
+    """Plan running an alternative factorisation order (ORDER_CT / ORDER_PEASE / ORDER_FOURSTEP)."""
     h = _vp()
     check(lib.fftc_plan_order(n, batch, direction, dtype_code(dtype), int(order), int(radix), ctypes.byref(h)),
           "fftc_plan_order")

@@ -13,7 +13,7 @@ def test_compiled_orders():
         got = fftc.compiled_orders(dt)
         want = {(n, o, r) for n, r in [(64, 2), (64, 4), (64, 8), (256, 2), (256, 4), (256, 16), (1024, 2),
                                         (1024, 4), (4096, 2), (4096, 4), (4096, 8), (4096, 16)]
-                for o in (fftc.ORDER_CT, fftc.ORDER_PEASE)}
+                for o in (fftc.ORDER_CT, fftc.ORDER_PEASE, fftc.ORDER_FOURSTEP)}
         assert set(got) == want
         for n, _, r in got:
             m = n
@@ -31,7 +31,7 @@ def _plan_status(n, order, radix, dtype="c64", batch=1, direction=fftc.FORWARD):
 
 def test_plan_order_errors():
     assert _plan_status(1024, 0, 2) == 1          # Stockham goes through fftc_plan
-    assert _plan_status(1024, 3, 2) == 1
+    assert _plan_status(1024, 4, 2) == 1          # no such order
     assert _plan_status(1024, fftc.ORDER_CT, 16) == 2   # 1024 is not a power of 16
     assert _plan_status(2048, fftc.ORDER_PEASE, 2) == 2  # not compiled
     assert _plan_status(1024, fftc.ORDER_CT, 2, dtype="split_f16") == 1
@@ -47,13 +47,15 @@ def test_tuning_db_order_lines(tmp_path):
                    "gfx950 c64 4096 ct:4,4 0.1\n"                  # does not multiply to n
                    "gfx950 c64 512 ct:2,2,2,2,2,2,2,2,2 0.1\n"     # not compiled
                    "gfx950 c128 64 ct:8,8 0.01\n"
+                   "gfx950 c128 4096 fourstep:16,16,16 0.03\n"
                    "gfx950 c64 256 16,16 0.02\n")
     try:
-        assert fftc.tune_load(str(src)) == 3
+        assert fftc.tune_load(str(src)) == 4
         out = tmp_path / "out.txt"
-        assert fftc.tune_save(str(out)) == 3
+        assert fftc.tune_save(str(out)) == 4
         text = out.read_text()
         assert "c64 1024 pease:4,4,4,4,4" in text and "c128 64 ct:8,8" in text and "c64 256 16,16" in text
+        assert "c128 4096 fourstep:16,16,16" in text
         # an order entry is not a Stockham list: the planner's own choice stays
         assert fftc.factorize(1024)[0] == fftc.candidates(1024)[0]
         assert fftc.factorize(256)[0] == [16, 16]
