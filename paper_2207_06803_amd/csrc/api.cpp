@@ -218,7 +218,7 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
             launch_shape(m, p->r1, (int)cs, &tpt1, &tdummy);
             launch_shape(k, p->r2, (int)cs, &tpt2, &tdummy);
             if (tpt1 * tc > 1024 || tpt2 * tc > 1024 ||
-                (size_t)tc * lds_len((int)std::max(m, k)) * cs > (size_t)kLdsMaxPerGroup)
+                (size_t)tc * tile_pitch((int)std::max(m, k)) * cs > (size_t)kLdsMaxPerGroup)
                 st = fail(FFTC_ERR_UNSUPPORTED_SIZE, "two-pass tile does not fit a workgroup");
             if (st == FFTC_OK) {
                 std::vector<TwSegment> segs;

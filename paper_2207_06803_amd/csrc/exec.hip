@@ -52,7 +52,7 @@ four_step_pass(const cplx<Real>* src, cplx<Real>* dst, const cplx<Real>* __restr
     using C = cplx<Real>;
     C* lds = reinterpret_cast<C*>(fftc_dyn_lds);
     const int len = d.n;             // transform length of this pass
-    const int ldl = lds_len(len);
+    const int ldl = tile_pitch(len);
     const int col0 = (int)blockIdx.x * tc;
     const int cols = min(tc, ncols - col0);
     const int64_t base = (int64_t)blockIdx.y * n;
@@ -326,7 +326,7 @@ static fftc_status launch_two_pass_chunk(const fftc_plan_s* p, const cplx<Real>*
     } else {
         const GenDesc& d = p->pass1;
         dim3 grid((unsigned)((p->k + tc - 1) / tc), (unsigned)nb);
-        const size_t lds = (size_t)tc * lds_len(d.n) * csz;
+        const size_t lds = (size_t)tc * tile_pitch(d.n) * csz;
         hipLaunchKernelGGL((four_step_pass<Real, INV, 1>), grid, dim3(d.tpt * tc), lds, s, tin, mid, tw,
                            twn, d, p->n, (int)p->k, tc, mul_for(d.n));
         hipError_t e = hipGetLastError();
@@ -345,7 +345,7 @@ static fftc_status launch_two_pass_chunk(const fftc_plan_s* p, const cplx<Real>*
     } else {
         const GenDesc& d = p->pass2;
         dim3 grid((unsigned)((p->m + tc - 1) / tc), (unsigned)nb);
-        const size_t lds = (size_t)tc * lds_len(d.n) * csz;
+        const size_t lds = (size_t)tc * tile_pitch(d.n) * csz;
         hipLaunchKernelGGL((four_step_pass<Real, INV, 2>), grid, dim3(d.tpt * tc), lds, s,
                            (const C*)mid, tout, tw, twn, d, p->n, (int)p->m, tc, mul_for(d.n));
         hipError_t e = hipGetLastError();

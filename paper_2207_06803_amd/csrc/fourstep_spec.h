@@ -17,7 +17,7 @@ fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C*
               const typename K::C* __restrict__ twn, int64_t n, int ncols) {
     using C = typename K::C;
     constexpr int LEN = K::N, TPT = K::TPT, TC = K::T, NTH = TPT * TC;
-    constexpr int LDSN = lds_len(LEN);
+    constexpr int LDSN = tile_pitch(LEN);
     constexpr int TOT = TC * LEN, IT = (TOT + NTH - 1) / NTH;
     __shared__ C lds[TC * LDSN];
     const int tid = (int)threadIdx.x;
@@ -97,7 +97,7 @@ struct FourStepInst {
     static constexpr int rs[sizeof...(Rs)] = {Rs...};
     static constexpr int TPT = round_tpt(required_tpt(N, rs, (int)sizeof...(Rs)));
     static_assert(TPT * TC <= 1024, "four-step tile too large");
-    static_assert(TC * lds_len(N) * (int)sizeof(cplx<Real>) <= kLdsMaxPerGroup, "four-step LDS too large");
+    static_assert(TC * tile_pitch(N) * (int)sizeof(cplx<Real>) <= kLdsMaxPerGroup, "four-step LDS too large");
     using K = SpecCfg<Real, N, TPT, TC, false>;
     static FourStepEntry entry(int dtype) {
         FourStepEntry e{dtype, N, (int)sizeof...(Rs), {Rs...}, TPT, TC, {}};

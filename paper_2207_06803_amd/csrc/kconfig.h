@@ -12,6 +12,11 @@ constexpr int kLdsMaxPerGroup = 163840;  // gfx950: 160 KB per workgroup
 // LDS elements for one transform: one pad element every 16.
 __host__ __device__ constexpr int lds_len(int n) { return n + (n >> 4); }
 
+// LDS elements per transform in a column tile (kernels whose HBM side moves
+// rows of adjacent transforms): the padded length made odd, so the tile's
+// transforms at one element index fall in different banks.
+__host__ __device__ constexpr int tile_pitch(int n) { return lds_len(n) | 1; }
+
 // Butterflies of radix r one thread holds at most in a stage.
 __host__ __device__ constexpr int nb_cap(int r) { return r >= kMaxElemsPerThread ? 1 : kMaxElemsPerThread / r; }
 

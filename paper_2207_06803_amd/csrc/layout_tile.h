@@ -17,7 +17,7 @@ stockham_tile_layout(GAcc<typename K::RealT> in, GAcc<typename K::RealT> out,
                      const typename K::C* __restrict__ tw, int64_t batch, int in_cols, int out_cols) {
     using C = typename K::C;
     constexpr int LEN = K::N, TPT = K::TPT, TC = K::T, NTH = TPT * TC;
-    constexpr int LDSN = lds_len(LEN);
+    constexpr int LDSN = tile_pitch(LEN);
     constexpr int TOT = TC * LEN, IT = (TOT + NTH - 1) / NTH;
     __shared__ C lds[TC * LDSN];
     const int tid = (int)threadIdx.x;
@@ -66,7 +66,7 @@ col_two_pass(GAcc<typename K::RealT> in, GAcc<typename K::RealT> out, typename K
              int other) {
     using C = typename K::C;
     constexpr int LEN = K::N, TPT = K::TPT, TC = K::T, NTH = TPT * TC;
-    constexpr int LDSN = lds_len(LEN);
+    constexpr int LDSN = tile_pitch(LEN);
     constexpr int TOT = TC * LEN, IT = (TOT + NTH - 1) / NTH;
     __shared__ C lds[TC * LDSN];
     const int tid = (int)threadIdx.x;
@@ -115,7 +115,7 @@ struct ColPassInst {
     static constexpr int rs[sizeof...(Rs)] = {Rs...};
     static constexpr int TPT = round_tpt(required_tpt(N, rs, (int)sizeof...(Rs)));
     static_assert(TPT * TC <= 1024, "column tile too large");
-    static_assert(TC * lds_len(N) * (int)sizeof(cplx<Real>) <= kLdsMaxPerGroup, "column tile LDS");
+    static_assert(TC * tile_pitch(N) * (int)sizeof(cplx<Real>) <= kLdsMaxPerGroup, "column tile LDS");
     using K = SpecCfg<Real, N, TPT, TC, false>;
     static FourStepEntry entry(int dtype) {
         FourStepEntry e{dtype, N, (int)sizeof...(Rs), {Rs...}, TPT, TC, {}};
@@ -130,7 +130,7 @@ struct ColPassInst {
 // Transforms per tile: 128 contiguous bytes per row where LDS allows.
 constexpr int tile_cols(int n, int csize) {
     int tc = 128 / csize;
-    while (tc > 1 && tc * lds_len(n) * csize > kLdsMaxPerGroup) tc /= 2;
+    while (tc > 1 && tc * tile_pitch(n) * csize > kLdsMaxPerGroup) tc /= 2;
     return tc;
 }
 
