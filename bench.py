@@ -364,21 +364,27 @@ def config4(torch, fftc, synth, timer):
                         "per transform against the complex128 GPU path", "by_n": out}
 
 
-def copy_ceiling(torch, synth, timer):
+def copy_ceiling(torch, fftc, synth, timer):
     """What a plain device copy reaches over the same rotating 1 GiB of
-    buffers as the headline (torch's copy kernel, 128 MiB in + 128 MiB out)."""
+    buffers as the headline (128 MiB in + 128 MiB out): torch's copy kernel,
+    and fftc_copy (16-byte nontemporal accesses, the transforms' own form).
+    `gbs` is the faster of the two."""
     xs = [torch.from_numpy(synth.uniform_complex(synth.rng(9), (ELEMS,), np.complex64)).to("cuda")
           for _ in range(NBUF)]
     ys = [torch.empty_like(xs[0]) for _ in range(NBUF)]
-    avg = timer.avg_ms(lambda i: ys[i % NBUF].copy_(xs[i % NBUF]), 20)
+    t_torch = timer.avg_ms(lambda i: ys[i % NBUF].copy_(xs[i % NBUF]), 20)
+    t_nt = timer.avg_ms(lambda i: fftc.copy(xs[i % NBUF], ys[i % NBUF], 8 * ELEMS, timer.s), 20)
     del xs, ys
     torch.cuda.empty_cache()
-    return {"workload": "torch copy_ of 2^24 complex64 over 4 rotating buffer pairs", "us": avg * 1e3,
-            "gbs": 16.0 * ELEMS / (avg * 1e-3) / 1e9}
+    rate = {k: 16.0 * ELEMS / (t * 1e-3) / 1e9 for k, t in (("torch_copy", t_torch), ("fftc_copy", t_nt))}
+    return {"workload": "device copy of 2^24 complex64 over 4 rotating buffer pairs",
+            "torch_copy": {"us": t_torch * 1e3, "gbs": rate["torch_copy"]},
+            "fftc_copy": {"us": t_nt * 1e3, "gbs": rate["fftc_copy"]},
+            "gbs": max(rate.values())}
 
 
 def launch_size(torch, fftc, synth, timer):
-    """The headline kernels and a plain copy at 2^22, 2^24 and 2^26 complex64
+    """The headline kernels and plain copies at 2^22, 2^24 and 2^26 complex64
     elements per launch (rotating buffers totalling >= 1 GiB): how much of a
     2^24-element launch goes to filling and draining the GPU."""
     out = {}
@@ -396,6 +402,8 @@ def launch_size(torch, fftc, synth, timer):
             row[f"c64_{n}_fwd"] = {"us": ms * 1e3, "hbm_gbs": 16.0 * e / (ms * 1e-3) / 1e9}
         ms = timer.avg_ms(lambda i: ys[i % nb].copy_(xs[i % nb]), 20)
         row["torch_copy"] = {"us": ms * 1e3, "hbm_gbs": 16.0 * e / (ms * 1e-3) / 1e9}
+        ms = timer.avg_ms(lambda i: fftc.copy(xs[i % nb], ys[i % nb], 8 * e, timer.s), 20)
+        row["fftc_copy"] = {"us": ms * 1e3, "hbm_gbs": 16.0 * e / (ms * 1e-3) / 1e9}
         out[f"2^{lg}"] = row
         del xs, ys
         torch.cuda.empty_cache()
@@ -739,7 +747,7 @@ def main():
                 "n": n_dom}
     extras = {}
     if not args.only_headline:
-        for name, fn in (("copy_ceiling", lambda: copy_ceiling(torch, synth, timer)),
+        for name, fn in (("copy_ceiling", lambda: copy_ceiling(torch, fftc, synth, timer)),
                          ("launch_size", lambda: launch_size(torch, fftc, synth, timer)),
                          ("config1_n64", lambda: config1(torch, fftc, synth, timer)),
                          ("c128", lambda: c128(torch, fftc, synth, timer)),

@@ -269,6 +269,18 @@ fftc_status fftc_compiled_entry(int dtype, int i, int64_t *n, int *radices, int 
 int64_t fftc_max_single_n(int dtype);
 
 /*
+ * Bandwidth reference (not an operation of the method): copy `bytes` from
+ * device memory `in` to device memory `out` in the transforms' own access
+ * form, one 16-byte nontemporal load and store per thread, asynchronously on
+ * `stream` (hipStream_t, NULL = default).  Both pointers 16-byte aligned and
+ * bytes a multiple of 16, the ranges disjoint; otherwise
+ * FFTC_ERR_INVALID_ARG and nothing is launched.  bytes = 0 does nothing.
+ * The caller owns both buffers.  The benchmark times it beside the
+ * transforms: what a plain stream of the same bytes reaches on the device.
+ */
+fftc_status fftc_copy(const void *in, void *out, size_t bytes, void *stream);
+
+/*
  * Mixed-length plan: `count` transforms of lengths n[0..count), packed back to
  * back in that order (transform i starts at element n[0] + ... + n[i-1]) in
  * both in and out.  Every length must satisfy 1 <= n[i] <= 4096 with prime

@@ -745,6 +745,20 @@ fftc_status fftc_factorize(int64_t n, int dtype, int* radices, int max_count, in
 
 int64_t fftc_max_single_n(int dtype) { return max_single_n(dtype); }
 
+fftc_status fftc_copy(const void* in, void* out, size_t bytes, void* stream) {
+    try {
+        if (bytes == 0) return FFTC_OK;
+        if (!in || !out) return fail(FFTC_ERR_INVALID_ARG, "NULL pointer");
+        if ((((uintptr_t)in | (uintptr_t)out | (uintptr_t)bytes) & 15) != 0)
+            return fail(FFTC_ERR_INVALID_ARG, "fftc_copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+        const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+        if (a < b + bytes && b < a + bytes) return fail(FFTC_ERR_INVALID_ARG, "fftc_copy ranges overlap");
+        return launch_copy16(in, out, (int64_t)(bytes / 16), static_cast<hipStream_t>(stream));
+    } catch (...) {
+        return fail(FFTC_ERR_INTERNAL, "exception in fftc_copy");
+    }
+}
+
 int fftc_compiled_count(int dtype) {
     if (dtype != FFTC_C64 && dtype != FFTC_C128) return 0;
     int total = 0;

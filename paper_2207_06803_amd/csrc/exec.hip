@@ -386,4 +386,25 @@ fftc_status enable_large_lds() {
     return FFTC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Bandwidth reference: a plain device copy in the transforms' access form
+// (one 16-byte nontemporal load and store per thread).
+// ---------------------------------------------------------------------------
+typedef float copy_vec __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) copy16(const copy_vec* __restrict__ in, copy_vec* __restrict__ out,
+                                              int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(in + i), out + i);
+}
+
+fftc_status launch_copy16(const void* in, void* out, int64_t nvec, hipStream_t s) {
+    const int64_t blocks = (nvec + 255) / 256;
+    if (!grid_fits(blocks)) return fail(FFTC_ERR_TOO_LARGE, "copy needs more workgroups than one launch holds");
+    hipLaunchKernelGGL(copy16, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const copy_vec*>(in),
+                       static_cast<copy_vec*>(out), nvec);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FFTC_OK : fail_hip(e, "launch(copy16)");
+}
+
 }  // namespace fftc

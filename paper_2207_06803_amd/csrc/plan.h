@@ -53,6 +53,7 @@ namespace fftc {
 // `batch` <= p->batch: run the first `batch` transforms.
 fftc_status launch_single(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);
 fftc_status launch_order(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s);
+fftc_status launch_copy16(const void* in, void* out, int64_t nvec, hipStream_t s);
 // Requests of one length in one launch (serving): `groups` workgroups in all.
 fftc_status launch_reqs(const SpecEntry* e, bool inv, const ReqList& list, int64_t groups, const void* tw,
                         hipStream_t s);

@@ -85,6 +85,7 @@ _SIGNATURES = {
     "fftc_factorize": (_int, [_i64, _int, ctypes.POINTER(_int), _int, ctypes.POINTER(_int),
                               ctypes.POINTER(_i64)]),
     "fftc_max_single_n": (_i64, [_int]),
+    "fftc_copy": (_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "fftc_compiled_count": (_int, [_int]),
     "fftc_compiled_entry": (_int, [_int, _int, ctypes.POINTER(_i64), ctypes.POINTER(_int), _int,
                                    ctypes.POINTER(_int)]),
@@ -416,6 +417,12 @@ def compiled_lists(dtype="c64"):
               "fftc_compiled_entry")
         out.append((n.value, list(arr[:cnt.value])))
     return out
+
+
+def copy(x, y, nbytes: int, stream=None) -> None:
+    """Device copy of nbytes from x to y with 16-byte nontemporal accesses
+    (the library's bandwidth reference)."""
+    check(lib.fftc_copy(ptr(x), ptr(y), int(nbytes), stream_handle(stream)), "fftc_copy")
 
 
 def max_single_n(dtype="c64") -> int:

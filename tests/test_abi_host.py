@@ -97,6 +97,12 @@ def test_bad_arguments_rejected_on_host():
     with pytest.raises(fftc.FFTCError) as e:
         fftc.Plan(64, 1, radices=[64])
     assert e.value.status == 1
+    # the copy reference checks its arguments before any launch
+    assert fftc.lib.fftc_copy(None, None, 0, None) == 0
+    assert fftc.lib.fftc_copy(1 << 20, (1 << 20) + 8, 16, None) == 1   # 8-byte aligned out
+    assert fftc.lib.fftc_copy(1 << 20, 2 << 20, 24, None) == 1          # not a multiple of 16
+    assert fftc.lib.fftc_copy(1 << 20, (1 << 20) + 16, 64, None) == 1   # overlapping ranges
+    assert fftc.lib.fftc_copy(None, 1 << 20, 16, None) == 1
     # NULL plan
     assert fftc.lib.fftc_execute(None, None, None, None) == 1
     assert fftc.lib.fftc_destroy_plan(None) == 0

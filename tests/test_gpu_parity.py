@@ -187,3 +187,13 @@ def test_eight_byte_offsets(n):
             scale = np.sqrt(n * (np.abs(x[row].astype(np.complex128)) ** 2).sum())
             err = np.linalg.norm(y[row, ks] - ref) / (scale * np.sqrt(len(ks) / n))
             assert err <= tol_for(n, "c64"), err
+
+
+def test_copy_reference():
+    """fftc_copy (the benchmark's bandwidth reference) copies bytes exactly."""
+    n = (1 << 20) + 3
+    x = torch.from_numpy(synth.uniform_complex(synth.rng(97), (n,), np.complex64)).to("cuda")
+    y = torch.zeros(n + 1, dtype=torch.complex64, device="cuda")
+    fftc.copy(x, y, 8 * (n - 1))  # 16-byte multiple: n - 1 elements
+    torch.cuda.synchronize()
+    assert torch.equal(y[:n - 1], x[:n - 1]) and not y[n - 1:].any()
