@@ -721,6 +721,8 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU: the library has no multi-GPU path "
                                    "(--gpus must be 1)", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    import __graft_entry__
+    __graft_entry__.ensure_built()  # only when nothing is built
     import torch
     from paper_2207_06803_amd import fftc, synth
 

@@ -8,3 +8,6 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    # build the library if nothing is built yet (an existing build is used as is)
+    import __graft_entry__
+    __graft_entry__.ensure_built()
