@@ -61,3 +61,58 @@ def test_tuning_db_order_lines(tmp_path):
         assert fftc.factorize(256)[0] == [16, 16]
     finally:
         fftc.tune_clear()
+
+
+def _fourstep_replay(x, n, r):
+    """The four-step order's steps in NumPy (Eq. 2 once, N = K M with
+    M = R^ceil(t/2), K = R^floor(t/2)): Pi^N_K as the load address, radix-R
+    Stockham stages on the K rows, D^N_M with the first column stage, radix-R
+    Stockham stages on the M stride-M columns."""
+    import numpy as np
+    t = round(np.log(n) / np.log(r))
+    tk = t // 2
+    tm = t - tk
+    m, k = r ** tm, r ** tk
+    w = np.exp(-2j * np.pi * np.arange(n) / n)
+    dft_r = np.exp(-2j * np.pi * np.outer(np.arange(r), np.arange(r)) / r)
+    a = np.empty(n, complex)
+    e = np.arange(n)
+    a[(e % k) * m + e // k] = x
+    for s in range(t):
+        b = np.empty(n, complex)
+        if s < tm:  # rows: stage s of DFT_M, ns = R^s
+            ns, mr = r ** s, m // r
+            bf = np.arange(n // r)
+            row, j = bf // mr, bf % mr
+            kk = j % ns
+            v = np.stack([a[row * m + j + q * mr] for q in range(r)])
+            if s:
+                v = v * np.stack([w[q * kk * (n // (ns * r))] for q in range(r)])
+            v = dft_r @ v
+            for q in range(r):
+                b[row * m + (j // ns) * ns * r + q * ns + kk] = v[q]
+        else:  # columns: stage s - tm of DFT_K; the first applies D^N_M
+            ns, kr = r ** (s - tm), k // r
+            bf = np.arange(n // r)
+            j, p = bf // m, bf % m
+            kk = j % ns
+            v = np.stack([a[(j + q * kr) * m + p] for q in range(r)])
+            if s == tm:
+                v = v * np.stack([w[(j + q * kr) * p] for q in range(r)])
+            else:
+                v = v * np.stack([w[q * kk * (n // (ns * r))] for q in range(r)])
+            v = dft_r @ v
+            for q in range(r):
+                b[((j // ns) * ns * r + q * ns + kk) * m + p] = v[q]
+        a = b
+    return a
+
+
+@pytest.mark.parametrize("n,r", [(64, 2), (64, 4), (64, 8), (256, 2), (256, 4), (256, 16), (1024, 2), (1024, 4),
+                                 (4096, 8), (4096, 16)])
+def test_fourstep_order_steps_are_a_dft(n, r):
+    import numpy as np
+    g = np.random.default_rng(n + r)
+    x = g.standard_normal(n) + 1j * g.standard_normal(n)
+    want = np.fft.fft(x)
+    assert np.abs(_fourstep_replay(x, n, r) - want).max() <= 1e-12 * np.abs(want).max()
