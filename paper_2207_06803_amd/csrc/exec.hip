@@ -1,5 +1,6 @@
 // Kernel launches for single-kernel and two-pass plans.
 #include <algorithm>
+#include <type_traits>
 
 #include "plan.h"
 
@@ -210,9 +211,20 @@ static GAcc<Real> make_acc(const fftc_layout& l, const void* re, const void* im)
     return a;
 }
 
+// Both sides interleaved: strides in complex elements.
 template <typename Real>
-static fftc_status launch_layout_cols(const fftc_plan_s* p, const GAcc<Real>& a, const GAcc<Real>& b, int64_t batch,
+static GAccI<Real> make_acc_i(const fftc_layout& l, const void* p) {
+    GAccI<Real> a;
+    a.p = static_cast<cplx<Real>*>(const_cast<void*>(p));
+    a.es = l.stride;
+    a.ts = l.dist;
+    return a;
+}
+
+template <typename Real, class ACC>
+static fftc_status launch_layout_cols(const fftc_plan_s* p, const ACC& a, const ACC& b, int64_t batch,
                                       hipStream_t s) {
+    constexpr bool IL = std::is_same<ACC, GAccI<Real>>::value;
     const bool inv = p->direction == FFTC_INVERSE;
     const cplx<Real>* tw = static_cast<const cplx<Real>*>(p->tw);
     const cplx<Real>* tw1 = tw + p->tw1_off;
@@ -224,13 +236,15 @@ static fftc_status launch_layout_cols(const fftc_plan_s* p, const GAcc<Real>& a,
     int k = (int)p->k, m = (int)p->m;
     const int64_t g1 = (batch + f1->tc - 1) / f1->tc, g2 = (batch + f2->tc - 1) / f2->tc;
     if (!grid_fits(g1) || !grid_fits(g2)) return fail(FFTC_ERR_INVALID_ARG, "batch too large for one launch");
-    GAcc<Real> aa = a, bb = b;
+    ACC aa = a, bb = b;
+    const void* fn1 = IL ? f1->fn_il[0][inv ? 1 : 0] : f1->fn[0][inv ? 1 : 0];
+    const void* fn2 = IL ? f2->fn_il[1][inv ? 1 : 0] : f2->fn[1][inv ? 1 : 0];
+    if (!fn1 || !fn2) return fail(FFTC_ERR_INTERNAL, "column-layout pass kernel missing");
     void* args1[] = {(void*)&aa, (void*)&bb, (void*)&scr, (void*)&tw1, (void*)&twn, (void*)&batch, (void*)&k};
-    hipError_t e = hipLaunchKernel(f1->fn[0][inv ? 1 : 0], dim3((unsigned)g1, (unsigned)k), dim3(f1->tpt * f1->tc),
-                                   args1, 0, s);
+    hipError_t e = hipLaunchKernel(fn1, dim3((unsigned)g1, (unsigned)k), dim3(f1->tpt * f1->tc), args1, 0, s);
     if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(col_two_pass 1)");
     void* args2[] = {(void*)&aa, (void*)&bb, (void*)&scr, (void*)&tw2, (void*)&twn, (void*)&batch, (void*)&m};
-    e = hipLaunchKernel(f2->fn[1][inv ? 1 : 0], dim3((unsigned)g2, (unsigned)m), dim3(f2->tpt * f2->tc), args2, 0, s);
+    e = hipLaunchKernel(fn2, dim3((unsigned)g2, (unsigned)m), dim3(f2->tpt * f2->tc), args2, 0, s);
     if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(col_two_pass 2)");
     return FFTC_OK;
 }
@@ -238,12 +252,18 @@ static fftc_status launch_layout_cols(const fftc_plan_s* p, const GAcc<Real>& a,
 fftc_status launch_layout(const fftc_plan_s* p, const void* in_re, const void* in_im, void* out_re, void* out_im,
                           int64_t batch, hipStream_t s) {
     const bool inv = p->direction == FFTC_INVERSE;
+    // both sides interleaved: the kernels with one vector access per element
+    const bool il = !p->lin.planar && !p->lout.planar;
     if (p->col1) {
         if (p->dtype == FFTC_C128)
-            return launch_layout_cols<double>(p, make_acc<double>(p->lin, in_re, in_im),
-                                              make_acc<double>(p->lout, out_re, out_im), batch, s);
-        return launch_layout_cols<float>(p, make_acc<float>(p->lin, in_re, in_im),
-                                         make_acc<float>(p->lout, out_re, out_im), batch, s);
+            return il ? launch_layout_cols<double>(p, make_acc_i<double>(p->lin, in_re),
+                                                   make_acc_i<double>(p->lout, out_re), batch, s)
+                      : launch_layout_cols<double>(p, make_acc<double>(p->lin, in_re, in_im),
+                                                   make_acc<double>(p->lout, out_re, out_im), batch, s);
+        return il ? launch_layout_cols<float>(p, make_acc_i<float>(p->lin, in_re), make_acc_i<float>(p->lout, out_re),
+                                              batch, s)
+                  : launch_layout_cols<float>(p, make_acc<float>(p->lin, in_re, in_im),
+                                              make_acc<float>(p->lout, out_re, out_im), batch, s);
     }
     // column-like sides (dist < stride) go through the tile kernel
     int in_cols = p->lin.dist < p->lin.stride ? 1 : 0, out_cols = p->lout.dist < p->lout.stride ? 1 : 0;
@@ -252,22 +272,38 @@ fftc_status launch_layout(const fftc_plan_s* p, const void* in_re, const void* i
     const int threads = tile ? p->spec->tile_tpt * p->spec->tile_tc : p->spec->tpt * p->spec->t;
     const int64_t groups = (batch + per - 1) / per;
     if (!grid_fits(groups)) return fail(FFTC_ERR_INVALID_ARG, "batch too large for one launch");
-    const void* fn = tile ? (inv ? p->spec->tile_inv : p->spec->tile_fwd) : (inv ? p->spec->inv : p->spec->fwd);
+    const void* fn = tile ? (il ? (inv ? p->spec->tile_il_inv : p->spec->tile_il_fwd)
+                                : (inv ? p->spec->tile_inv : p->spec->tile_fwd))
+                          : (il ? (inv ? p->spec->il_inv : p->spec->il_fwd) : (inv ? p->spec->inv : p->spec->fwd));
+    if (!fn) return fail(FFTC_ERR_INTERNAL, "layout kernel missing");
     hipError_t e;
+    // the tile kernel takes the two order flags as well
     if (p->dtype == FFTC_C128) {
-        GAcc<double> a = make_acc<double>(p->lin, in_re, in_im), b = make_acc<double>(p->lout, out_re, out_im);
         const double2* tw = static_cast<const double2*>(p->tw);
-        // the tile kernel takes the two order flags as well
-        void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch, (void*)&in_cols, (void*)&out_cols};
-        void* args4[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
-        e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), tile ? args : args4, 0, s);
+        if (il) {
+            GAccI<double> a = make_acc_i<double>(p->lin, in_re), b = make_acc_i<double>(p->lout, out_re);
+            void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch, (void*)&in_cols, (void*)&out_cols};
+            void* args4[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
+            e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), tile ? args : args4, 0, s);
+        } else {
+            GAcc<double> a = make_acc<double>(p->lin, in_re, in_im), b = make_acc<double>(p->lout, out_re, out_im);
+            void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch, (void*)&in_cols, (void*)&out_cols};
+            void* args4[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
+            e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), tile ? args : args4, 0, s);
+        }
     } else {
-        GAcc<float> a = make_acc<float>(p->lin, in_re, in_im), b = make_acc<float>(p->lout, out_re, out_im);
         const float2* tw = static_cast<const float2*>(p->tw);
-        // the tile kernel takes the two order flags as well
-        void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch, (void*)&in_cols, (void*)&out_cols};
-        void* args4[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
-        e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), tile ? args : args4, 0, s);
+        if (il) {
+            GAccI<float> a = make_acc_i<float>(p->lin, in_re), b = make_acc_i<float>(p->lout, out_re);
+            void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch, (void*)&in_cols, (void*)&out_cols};
+            void* args4[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
+            e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), tile ? args : args4, 0, s);
+        } else {
+            GAcc<float> a = make_acc<float>(p->lin, in_re, in_im), b = make_acc<float>(p->lout, out_re, out_im);
+            void* args[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch, (void*)&in_cols, (void*)&out_cols};
+            void* args4[] = {(void*)&a, (void*)&b, (void*)&tw, (void*)&batch};
+            e = hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), tile ? args : args4, 0, s);
+        }
     }
     if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(stockham_spec_layout)");
     return FFTC_OK;

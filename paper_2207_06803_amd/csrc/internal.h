@@ -60,6 +60,11 @@ struct SpecEntry {
     const void* tile_inv = nullptr;
     int tile_tpt = 0, tile_tc = 0;
     int tm = 0;  // transforms per 256-thread workgroup in the mixed kernel's body
+    // layout entries, both sides interleaved (one vector access per element)
+    const void* il_fwd = nullptr;
+    const void* il_inv = nullptr;
+    const void* tile_il_fwd = nullptr;
+    const void* tile_il_inv = nullptr;
 };
 // Compiled specialisations, in kSpecParts translation units per dtype.
 constexpr int kSpecParts = 4;
@@ -78,6 +83,7 @@ struct FourStepEntry {
     int radices[kMaxStages];
     int tpt, tc;
     const void* fn[2][2];  // [pass - 1][inverse]
+    const void* fn_il[2][2] = {};  // column-layout passes, both sides interleaved
 };
 const FourStepEntry* find_fourstep(int dtype, int64_t len, const std::vector<int>& rs);
 // Two-pass kernels for column-like layouts (layout_tile.h), same lengths.

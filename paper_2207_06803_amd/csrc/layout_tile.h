@@ -11,10 +11,10 @@
 
 namespace fftc {
 
-template <class K, bool INV, int... Rs>
+template <class K, bool INV, class ACC, int... Rs>
 __global__ void __launch_bounds__(K::TPT * K::T)
-stockham_tile_layout(GAcc<typename K::RealT> in, GAcc<typename K::RealT> out,
-                     const typename K::C* __restrict__ tw, int64_t batch, int in_cols, int out_cols) {
+stockham_tile_layout(ACC in, ACC out, const typename K::C* __restrict__ tw, int64_t batch, int in_cols,
+                     int out_cols) {
     using C = typename K::C;
     constexpr int LEN = K::N, TPT = K::TPT, TC = K::T, NTH = TPT * TC;
     constexpr int LDSN = tile_pitch(LEN);
@@ -59,9 +59,9 @@ stockham_tile_layout(GAcc<typename K::RealT> in, GAcc<typename K::RealT> out,
 //   pass 2 (blockIdx.y = p < M): v_i = scratch[(i M + p) B + c], i < K;
 //          DFT_K; y_c[p + q M], q < K
 // The inverse conjugates on pass 1's loads and pass 2's stores.
-template <class K, int PASS, bool INV, int... Rs>
+template <class K, int PASS, bool INV, class ACC, int... Rs>
 __global__ void __launch_bounds__(K::TPT * K::T)
-col_two_pass(GAcc<typename K::RealT> in, GAcc<typename K::RealT> out, typename K::C* scratch,
+col_two_pass(ACC in, ACC out, typename K::C* scratch,
              const typename K::C* __restrict__ tw, const typename K::C* __restrict__ twn, int64_t batch,
              int other) {
     using C = typename K::C;
@@ -119,10 +119,16 @@ struct ColPassInst {
     using K = SpecCfg<Real, N, TPT, TC, false>;
     static FourStepEntry entry(int dtype) {
         FourStepEntry e{dtype, N, (int)sizeof...(Rs), {Rs...}, TPT, TC, {}};
-        e.fn[0][0] = reinterpret_cast<const void*>(&col_two_pass<K, 1, false, Rs...>);
-        e.fn[0][1] = reinterpret_cast<const void*>(&col_two_pass<K, 1, true, Rs...>);
-        e.fn[1][0] = reinterpret_cast<const void*>(&col_two_pass<K, 2, false, Rs...>);
-        e.fn[1][1] = reinterpret_cast<const void*>(&col_two_pass<K, 2, true, Rs...>);
+        using GA = GAcc<Real>;
+        using GI = GAccI<Real>;
+        e.fn[0][0] = reinterpret_cast<const void*>(&col_two_pass<K, 1, false, GA, Rs...>);
+        e.fn[0][1] = reinterpret_cast<const void*>(&col_two_pass<K, 1, true, GA, Rs...>);
+        e.fn[1][0] = reinterpret_cast<const void*>(&col_two_pass<K, 2, false, GA, Rs...>);
+        e.fn[1][1] = reinterpret_cast<const void*>(&col_two_pass<K, 2, true, GA, Rs...>);
+        e.fn_il[0][0] = reinterpret_cast<const void*>(&col_two_pass<K, 1, false, GI, Rs...>);
+        e.fn_il[0][1] = reinterpret_cast<const void*>(&col_two_pass<K, 1, true, GI, Rs...>);
+        e.fn_il[1][0] = reinterpret_cast<const void*>(&col_two_pass<K, 2, false, GI, Rs...>);
+        e.fn_il[1][1] = reinterpret_cast<const void*>(&col_two_pass<K, 2, true, GI, Rs...>);
         return e;
     }
 };
@@ -143,8 +149,10 @@ struct TileInst {
     static_assert(TC >= 1 && TPT * TC <= 1024, "tile too large");
     using K = SpecCfg<Real, N, TPT, TC, false>;
     static void fill(SpecEntry* e) {
-        e->tile_fwd = reinterpret_cast<const void*>(&stockham_tile_layout<K, false, Rs...>);
-        e->tile_inv = reinterpret_cast<const void*>(&stockham_tile_layout<K, true, Rs...>);
+        e->tile_fwd = reinterpret_cast<const void*>(&stockham_tile_layout<K, false, GAcc<Real>, Rs...>);
+        e->tile_inv = reinterpret_cast<const void*>(&stockham_tile_layout<K, true, GAcc<Real>, Rs...>);
+        e->tile_il_fwd = reinterpret_cast<const void*>(&stockham_tile_layout<K, false, GAccI<Real>, Rs...>);
+        e->tile_il_inv = reinterpret_cast<const void*>(&stockham_tile_layout<K, true, GAccI<Real>, Rs...>);
         e->tile_tpt = TPT;
         e->tile_tc = TC;
     }

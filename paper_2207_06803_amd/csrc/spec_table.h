@@ -34,10 +34,14 @@ struct SpecInst {
                     reinterpret_cast<const void*>(&stockham_spec_reqs<KI, Rs...>), -1};
         return e;
     }
+    // general accessors (planar or interleaved sides), and both sides
+    // interleaved with one vector access per element
     static SpecEntry layout_entry(int dtype) {
         SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
-                    reinterpret_cast<const void*>(&stockham_spec_layout<KF, Rs...>),
-                    reinterpret_cast<const void*>(&stockham_spec_layout<KI, Rs...>), -1};
+                    reinterpret_cast<const void*>(&stockham_spec_layout<KF, GAcc<Real>, Rs...>),
+                    reinterpret_cast<const void*>(&stockham_spec_layout<KI, GAcc<Real>, Rs...>), -1};
+        e.il_fwd = reinterpret_cast<const void*>(&stockham_spec_layout<KF, GAccI<Real>, Rs...>);
+        e.il_inv = reinterpret_cast<const void*>(&stockham_spec_layout<KI, GAccI<Real>, Rs...>);
         return e;
     }
 };

@@ -71,6 +71,24 @@ template <bool INV, typename Real> __device__ __forceinline__ void gst(const GAc
     __builtin_nontemporal_store(v.y, a.im + o);
 }
 
+// Interleaved complex data at any element and transform strides (es, ts in
+// complex elements): one 8-byte (complex64) or 16-byte (complex128) access
+// per element, where GAcc would make two of half the width.
+template <typename Real> struct GAccI {
+    cplx<Real>* p;
+    int64_t es, ts;
+};
+template <typename Real> __device__ __forceinline__ GAccI<Real> gshift(GAccI<Real> a, int64_t q) {
+    a.p += q * a.ts;
+    return a;
+}
+template <bool INV, typename Real> __device__ __forceinline__ cplx<Real> gld(const GAccI<Real>& a, int e) {
+    return ld_in<INV>(a.p + (int64_t)e * a.es);
+}
+template <bool INV, typename Real> __device__ __forceinline__ void gst(const GAccI<Real>& a, int e, cplx<Real> v) {
+    st_out<INV>(a.p + (int64_t)e * a.es, v);
+}
+
 // Multiply v[r] (r >= 1) by w_{Ns R}^{r k}, with tq = table + k (entry
 // [(r-1) Ns + k] at tq[(r-1) ns]).  For R = 8 and 16 only the factors
 // r = 1, 2, 3 and r = 4, 8, 12 are read and the rest formed as one product
@@ -350,10 +368,9 @@ struct IndexOff {
     __device__ __forceinline__ int64_t operator()(int q) const { return base + q; }
 };
 
-template <class K, int... Rs>
+template <class K, class ACC, int... Rs>
 __global__ void __launch_bounds__(K::TPT * K::T)
-stockham_spec_layout(GAcc<typename K::RealT> in, GAcc<typename K::RealT> out,
-                     const typename K::C* __restrict__ tw, int64_t batch) {
+stockham_spec_layout(ACC in, ACC out, const typename K::C* __restrict__ tw, int64_t batch) {
     using C = typename K::C;
     constexpr int T = K::T, NTH = K::TPT * K::T;
     __shared__ C lds[T * SpecLds<K, sizeof...(Rs)>::LDSN];
