@@ -277,6 +277,32 @@ fftc_status launch_layout(const fftc_plan_s* p, const void* in_re, const void* i
                           : (il ? (inv ? p->spec->il_inv : p->spec->il_fwd) : (inv ? p->spec->inv : p->spec->fwd));
     if (!fn) return fail(FFTC_ERR_INTERNAL, "layout kernel missing");
     hipError_t e;
+    // one side planar, the other interleaved (row layouts): the interleaved
+    // side takes its own accessor
+    const bool mixed_pi = !tile && p->lin.planar && !p->lout.planar && p->spec->pi_fwd;
+    const bool mixed_ip = !tile && !p->lin.planar && p->lout.planar && p->spec->ip_fwd;
+    if (mixed_pi || mixed_ip) {
+        const void* fm = mixed_pi ? (inv ? p->spec->pi_inv : p->spec->pi_fwd) : (inv ? p->spec->ip_inv : p->spec->ip_fwd);
+        if (p->dtype == FFTC_C128) {
+            const double2* tw = static_cast<const double2*>(p->tw);
+            GAcc<double> ga = make_acc<double>(mixed_pi ? p->lin : p->lout, mixed_pi ? in_re : out_re,
+                                               mixed_pi ? in_im : out_im);
+            GAccI<double> gi = make_acc_i<double>(mixed_pi ? p->lout : p->lin, mixed_pi ? out_re : in_re);
+            void* args_pi[] = {(void*)&ga, (void*)&gi, (void*)&tw, (void*)&batch};
+            void* args_ip[] = {(void*)&gi, (void*)&ga, (void*)&tw, (void*)&batch};
+            e = hipLaunchKernel(fm, dim3((unsigned)groups), dim3(threads), mixed_pi ? args_pi : args_ip, 0, s);
+        } else {
+            const float2* tw = static_cast<const float2*>(p->tw);
+            GAcc<float> ga = make_acc<float>(mixed_pi ? p->lin : p->lout, mixed_pi ? in_re : out_re,
+                                             mixed_pi ? in_im : out_im);
+            GAccI<float> gi = make_acc_i<float>(mixed_pi ? p->lout : p->lin, mixed_pi ? out_re : in_re);
+            void* args_pi[] = {(void*)&ga, (void*)&gi, (void*)&tw, (void*)&batch};
+            void* args_ip[] = {(void*)&gi, (void*)&ga, (void*)&tw, (void*)&batch};
+            e = hipLaunchKernel(fm, dim3((unsigned)groups), dim3(threads), mixed_pi ? args_pi : args_ip, 0, s);
+        }
+        if (e != hipSuccess) return fail_hip(e, "hipLaunchKernel(stockham_spec_layout)");
+        return FFTC_OK;
+    }
     // the tile kernel takes the two order flags as well
     if (p->dtype == FFTC_C128) {
         const double2* tw = static_cast<const double2*>(p->tw);

@@ -65,6 +65,11 @@ struct SpecEntry {
     const void* il_inv = nullptr;
     const void* tile_il_fwd = nullptr;
     const void* tile_il_inv = nullptr;
+    // planar in / interleaved out, and interleaved in / planar out
+    const void* pi_fwd = nullptr;
+    const void* pi_inv = nullptr;
+    const void* ip_fwd = nullptr;
+    const void* ip_inv = nullptr;
 };
 // Compiled specialisations, in kSpecParts translation units per dtype.
 constexpr int kSpecParts = 4;

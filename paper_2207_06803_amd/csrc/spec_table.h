@@ -34,14 +34,21 @@ struct SpecInst {
                     reinterpret_cast<const void*>(&stockham_spec_reqs<KI, Rs...>), -1};
         return e;
     }
-    // general accessors (planar or interleaved sides), and both sides
-    // interleaved with one vector access per element
+    // general accessors on both sides (planar or interleaved), and the
+    // interleaved accessor (one vector access per element) on the
+    // interleaved side(s): [in interleaved][out interleaved]
     static SpecEntry layout_entry(int dtype) {
+        using GA = GAcc<Real>;
+        using GI = GAccI<Real>;
         SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
-                    reinterpret_cast<const void*>(&stockham_spec_layout<KF, GAcc<Real>, Rs...>),
-                    reinterpret_cast<const void*>(&stockham_spec_layout<KI, GAcc<Real>, Rs...>), -1};
-        e.il_fwd = reinterpret_cast<const void*>(&stockham_spec_layout<KF, GAccI<Real>, Rs...>);
-        e.il_inv = reinterpret_cast<const void*>(&stockham_spec_layout<KI, GAccI<Real>, Rs...>);
+                    reinterpret_cast<const void*>(&stockham_spec_layout<KF, GA, GA, Rs...>),
+                    reinterpret_cast<const void*>(&stockham_spec_layout<KI, GA, GA, Rs...>), -1};
+        e.il_fwd = reinterpret_cast<const void*>(&stockham_spec_layout<KF, GI, GI, Rs...>);
+        e.il_inv = reinterpret_cast<const void*>(&stockham_spec_layout<KI, GI, GI, Rs...>);
+        e.pi_fwd = reinterpret_cast<const void*>(&stockham_spec_layout<KF, GA, GI, Rs...>);
+        e.pi_inv = reinterpret_cast<const void*>(&stockham_spec_layout<KI, GA, GI, Rs...>);
+        e.ip_fwd = reinterpret_cast<const void*>(&stockham_spec_layout<KF, GI, GA, Rs...>);
+        e.ip_inv = reinterpret_cast<const void*>(&stockham_spec_layout<KI, GI, GA, Rs...>);
         return e;
     }
 };

@@ -368,9 +368,9 @@ struct IndexOff {
     __device__ __forceinline__ int64_t operator()(int q) const { return base + q; }
 };
 
-template <class K, class ACC, int... Rs>
+template <class K, class AI, class AO, int... Rs>
 __global__ void __launch_bounds__(K::TPT * K::T)
-stockham_spec_layout(ACC in, ACC out, const typename K::C* __restrict__ tw, int64_t batch) {
+stockham_spec_layout(AI in, AO out, const typename K::C* __restrict__ tw, int64_t batch) {
     using C = typename K::C;
     constexpr int T = K::T, NTH = K::TPT * K::T;
     __shared__ C lds[T * SpecLds<K, sizeof...(Rs)>::LDSN];
