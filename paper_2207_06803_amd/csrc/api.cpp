@@ -97,7 +97,11 @@ static fftc_status plan_order_impl(int64_t n, int64_t batch, int direction, int 
     p->batch = batch;
     p->direction = direction;
     p->dtype = dtype;
-    hipGetDevice(&p->device);
+    const hipError_t de = hipGetDevice(&p->device);
+    if (de != hipSuccess) {
+        delete p;
+        return fail_hip(de, "hipGetDevice");
+    }
     p->variant = FFTC_VARIANT_ORDER;
     p->order = o;
     p->tpt = o->tpt;
@@ -164,7 +168,11 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
     p->batch = batch;
     p->direction = direction;
     p->dtype = dtype;
-    hipGetDevice(&p->device);
+    const hipError_t de = hipGetDevice(&p->device);
+    if (de != hipSuccess) {
+        delete p;
+        return fail_hip(de, "hipGetDevice");
+    }
     const size_t cs = csize_of(dtype);
 
     if (is_split_dtype(dtype)) {

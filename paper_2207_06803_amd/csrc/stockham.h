@@ -71,6 +71,39 @@ template <bool INV, typename Real> __device__ __forceinline__ void gst(const GAc
     __builtin_nontemporal_store(v.y, a.im + o);
 }
 
+// The planar accessor with ordinary (cached) accesses, for kernels whose
+// wave covers fewer than 128 bytes of one array per access (fewer than 32
+// threads per transform): each cache line is then reached by two accesses,
+// and the second must find it in the cache.
+template <typename Real> struct GAccT : GAcc<Real> {};
+template <typename Real> __device__ __forceinline__ GAccT<Real> gshift(GAccT<Real> a, int64_t q) {
+    a.re += q * a.ts;
+    a.im += q * a.ts;
+    return a;
+}
+template <bool INV, typename Real> __device__ __forceinline__ cplx<Real> gld(const GAccT<Real>& a, int e) {
+    const int64_t o = (int64_t)e * a.es;
+    cplx<Real> v = mk(a.re[o], a.im[o]);
+    return INV ? cconj(v) : v;
+}
+template <bool INV, typename Real> __device__ __forceinline__ void gst(const GAccT<Real>& a, int e, cplx<Real> v) {
+    const int64_t o = (int64_t)e * a.es;
+    if (INV) v = cconj(v);
+    a.re[o] = v.x;
+    a.im[o] = v.y;
+}
+// Planar sides of short-row kernels use the cached accessor.
+template <class K, class A> struct LayoutAcc { using type = A; };
+template <class K> struct LayoutAcc<K, GAcc<typename K::RealT>> {
+    using type = typename std::conditional<(K::TPT < 32 && !K::STAGED), GAccT<typename K::RealT>,
+                                           GAcc<typename K::RealT>>::type;
+};
+template <class K, class A> __device__ __forceinline__ typename LayoutAcc<K, A>::type layout_acc(const A& a) {
+    typename LayoutAcc<K, A>::type r;
+    static_cast<A&>(r) = a;
+    return r;
+}
+
 // Interleaved complex data at any element and transform strides (es, ts in
 // complex elements): one 8-byte (complex64) or 16-byte (complex128) access
 // per element, where GAcc would make two of half the width.
@@ -376,7 +409,8 @@ stockham_spec_layout(AI in, AO out, const typename K::C* __restrict__ tw, int64_
     __shared__ C lds[T * SpecLds<K, sizeof...(Rs)>::LDSN];
     const int64_t b0 = (int64_t)blockIdx.x * T;
     const int count = (int)min((int64_t)T, batch - b0);
-    spec_group<K, NTH, IndexOff, Rs...>(in, out, IndexOff{b0}, count, lds, tw, (int)threadIdx.x);
+    spec_group<K, NTH, IndexOff, Rs...>(layout_acc<K>(in), layout_acc<K>(out), IndexOff{b0}, count, lds, tw,
+                                        (int)threadIdx.x);
 }
 
 }  // namespace fftc
