@@ -72,9 +72,9 @@ template <bool INV, typename Real> __device__ __forceinline__ void gst(const GAc
 }
 
 // The planar accessor with ordinary (cached) accesses, for kernels whose
-// wave covers fewer than 128 bytes of one array per access (fewer than 32
-// threads per transform): each cache line is then reached by two accesses,
-// and the second must find it in the cache.
+// lanes on one transform cover fewer than 128 bytes of one array per access
+// (fewer than 32 threads per complex64 transform): each cache line is then
+// reached by two accesses, and the second must find it in the cache.
 template <typename Real> struct GAccT : GAcc<Real> {};
 template <typename Real> __device__ __forceinline__ GAccT<Real> gshift(GAccT<Real> a, int64_t q) {
     a.re += q * a.ts;
@@ -95,8 +95,8 @@ template <bool INV, typename Real> __device__ __forceinline__ void gst(const GAc
 // Planar sides of short-row kernels use the cached accessor.
 template <class K, class A> struct LayoutAcc { using type = A; };
 template <class K> struct LayoutAcc<K, GAcc<typename K::RealT>> {
-    using type = typename std::conditional<(K::TPT < 32 && !K::STAGED), GAccT<typename K::RealT>,
-                                           GAcc<typename K::RealT>>::type;
+    using type = typename std::conditional<(K::TPT * (int)sizeof(typename K::RealT) < 128 && !K::STAGED),
+                                           GAccT<typename K::RealT>, GAcc<typename K::RealT>>::type;
 };
 template <class K, class A> __device__ __forceinline__ typename LayoutAcc<K, A>::type layout_acc(const A& a) {
     typename LayoutAcc<K, A>::type r;
