@@ -237,14 +237,15 @@ def config1(torch, fftc, synth, timer):
 
 
 def c128(torch, fftc, synth, timer):
-    xs = [torch.from_numpy(synth.uniform_complex(synth.rng(1, 1), (ELEMS,), np.complex128)).to("cuda")
-          for _ in range(2)]
-    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    x0 = torch.from_numpy(synth.uniform_complex(synth.rng(1, 1), (ELEMS,), np.complex128)).to("cuda")
+    xs = [x0.clone() for _ in range(NBUF)]  # rotating, as for the headline
+    ys = [torch.empty_like(x0) for _ in range(NBUF)]
+    del x0
     out = {}
     for n in SIZES:
         for d in (fftc.FORWARD, fftc.INVERSE):
             with fftc.Plan(n, ELEMS // n, d, "c128") as p:
-                avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % 2], ys[i % 2], timer.s), 10)
+                avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % NBUF], ys[i % NBUF], timer.s), 10)
             out[f"c128_{n}_{'fwd' if d < 0 else 'inv'}"] = {
                 "us": avg * 1e3, "gflops": flops(n, ELEMS // n) / (avg * 1e-3) / 1e9,
                 "hbm_gbs": 32.0 * ELEMS / (avg * 1e-3) / 1e9}
@@ -255,14 +256,15 @@ def c128(torch, fftc, synth, timer):
 
 def two_pass(torch, fftc, synth, timer):
     """Lengths beyond one workgroup's LDS (Eq. 2 four-step, two kernels)."""
-    xs = [torch.from_numpy(synth.uniform_complex(synth.rng(1, 2), (ELEMS,), np.complex64)).to("cuda")
-          for _ in range(2)]
-    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    x0 = torch.from_numpy(synth.uniform_complex(synth.rng(1, 2), (ELEMS,), np.complex64)).to("cuda")
+    xs = [x0.clone() for _ in range(NBUF)]  # rotating, as for the headline
+    ys = [torch.empty_like(x0) for _ in range(NBUF)]
+    del x0
     out = {}
     for n in (32768, 65536, 1 << 20):
         with fftc.Plan(n, ELEMS // n, fftc.FORWARD, "c64") as p:
             d = p.describe()
-            avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % 2], ys[i % 2], timer.s), 10)
+            avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % NBUF], ys[i % NBUF], timer.s), 10)
         out[f"c64_{n}_fwd"] = {"us": avg * 1e3, "gflops": flops(n, ELEMS // n) / (avg * 1e-3) / 1e9,
                                "hbm_gbs_algorithmic": 16.0 * ELEMS / (avg * 1e-3) / 1e9,
                                "hbm_gbs_moved": 32.0 * ELEMS / (avg * 1e-3) / 1e9,
@@ -413,9 +415,10 @@ def launch_size(torch, fftc, synth, timer):
 def formula(torch, fftc, synth, timer):
     """Formula plans at 2^24 complex64 elements per launch."""
     from paper_2207_06803_amd import formulas as F
-    xs = [torch.from_numpy(synth.uniform_complex(synth.rng(6), (ELEMS,), np.complex64)).to("cuda")
-          for _ in range(2)]
-    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    x0 = torch.from_numpy(synth.uniform_complex(synth.rng(6), (ELEMS,), np.complex64)).to("cuda")
+    xs = [x0.clone() for _ in range(NBUF)]  # rotating, as for the headline
+    ys = [torch.empty_like(x0) for _ in range(NBUF)]
+    del x0
     NF, EQ2 = fftc.FORMULA_NO_FOLD, fftc.FORMULA_EQ2
     cases = [
         ("listing1_folded", F.recursive_ct(4), 0), ("listing1_as_written", F.recursive_ct(4), NF),
@@ -431,12 +434,12 @@ def formula(torch, fftc, synth, timer):
         dim = fftc.formula_lower(text, flags)[0]
         with fftc.plan_formula(text, ELEMS // dim, fftc.FORWARD, "c64", flags) as p:
             d = p.describe()
-            avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % 2], ys[i % 2], timer.s), 10)
+            avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % NBUF], ys[i % NBUF], timer.s), 10)
         out[name] = {"dim": dim, "us": avg * 1e3, "hbm_gbs_algorithmic": 16.0 * ELEMS / (avg * 1e-3) / 1e9,
                      "folded": d["formula_folded"], "passes": d["formula_passes"],
                      "kernels": 1 if d["formula_folded"] else d["formula_kernels"]}
     with fftc.Plan(1024, ELEMS // 1024, fftc.FORWARD, "c64") as p:
-        out["plan_1024_reference_us"] = timer.avg_ms(lambda i: p.execute(xs[i % 2], ys[i % 2], timer.s), 10) * 1e3
+        out["plan_1024_reference_us"] = timer.avg_ms(lambda i: p.execute(xs[i % NBUF], ys[i % NBUF], timer.s), 10) * 1e3
     del xs, ys
     torch.cuda.empty_cache()
     return {"workload": "complex64 forward, 2^24 elements per launch; algorithmic bytes = one read and one "
@@ -448,26 +451,28 @@ def layouts(torch, fftc, synth, timer):
     E = ELEMS
     g = synth.rng(7)
     host = synth.uniform_complex(g, (E,), np.complex64)
-    re = [torch.from_numpy(np.ascontiguousarray(host.real)).to("cuda") for _ in range(2)]
-    im = [torch.from_numpy(np.ascontiguousarray(host.imag)).to("cuda") for _ in range(2)]
-    ore, oim = [torch.empty_like(re[0]) for _ in range(2)], [torch.empty_like(re[0]) for _ in range(2)]
-    cx = [torch.from_numpy(host).to("cuda") for _ in range(2)]
-    cy = [torch.empty_like(cx[0]) for _ in range(2)]
+    # NBUF rotating buffer sets (1 GiB of inputs and outputs per layout kind),
+    # as for the headline, so the last-level cache cannot serve the reads
+    re = [torch.from_numpy(np.ascontiguousarray(host.real)).to("cuda") for _ in range(NBUF)]
+    im = [torch.from_numpy(np.ascontiguousarray(host.imag)).to("cuda") for _ in range(NBUF)]
+    ore, oim = [torch.empty_like(re[0]) for _ in range(NBUF)], [torch.empty_like(re[0]) for _ in range(NBUF)]
+    cx = [torch.from_numpy(host).to("cuda") for _ in range(NBUF)]
+    cy = [torch.empty_like(cx[0]) for _ in range(NBUF)]
     out = {}
     for n in (256, 1024, 4096):
         b = E // n
         row = {}
         with fftc.Plan(n, b, fftc.FORWARD, "c64") as p:
-            row["interleaved_us"] = timer.avg_ms(lambda i: p.execute(cx[i % 2], cy[i % 2], timer.s), 10) * 1e3
+            row["interleaved_us"] = timer.avg_ms(lambda i: p.execute(cx[i % NBUF], cy[i % NBUF], timer.s), 10) * 1e3
         with fftc.plan_layout(n, b, fftc.FORWARD, "c64", (1, n, 1), (1, n, 1)) as p:
             row["planar_us"] = timer.avg_ms(
-                lambda i: fftc.execute_layout(p, re[i % 2], im[i % 2], ore[i % 2], oim[i % 2], timer.s), 10) * 1e3
+                lambda i: fftc.execute_layout(p, re[i % NBUF], im[i % NBUF], ore[i % NBUF], oim[i % NBUF], timer.s), 10) * 1e3
         with fftc.plan_layout(n, b, fftc.FORWARD, "c64", (1, n, 1), None) as p:
             row["planar_to_interleaved_us"] = timer.avg_ms(
-                lambda i: fftc.execute_layout(p, re[i % 2], im[i % 2], cy[i % 2], None, timer.s), 10) * 1e3
+                lambda i: fftc.execute_layout(p, re[i % NBUF], im[i % NBUF], cy[i % NBUF], None, timer.s), 10) * 1e3
         with fftc.plan_layout(n, b, fftc.FORWARD, "c64", (b, 1, 0), (b, 1, 0)) as p:
             row["columns_us"] = timer.avg_ms(
-                lambda i: fftc.execute_layout(p, cx[i % 2], None, cy[i % 2], None, timer.s), 5) * 1e3
+                lambda i: fftc.execute_layout(p, cx[i % NBUF], None, cy[i % NBUF], None, timer.s), 5) * 1e3
         for k in list(row):
             row[k.replace("_us", "_gbs")] = 16.0 * E / (row[k] * 1e-6) / 1e9
         out[str(n)] = row
@@ -479,22 +484,23 @@ def layouts(torch, fftc, synth, timer):
 
 def orders(torch, fftc, synth, timer):
     """Stockham against the alternative orders at 2^24 complex64 elements."""
-    xs = [torch.from_numpy(synth.uniform_complex(synth.rng(8), (ELEMS,), np.complex64)).to("cuda")
-          for _ in range(2)]
-    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    x0 = torch.from_numpy(synth.uniform_complex(synth.rng(8), (ELEMS,), np.complex64)).to("cuda")
+    xs = [x0.clone() for _ in range(NBUF)]  # rotating, as for the headline
+    ys = [torch.empty_like(x0) for _ in range(NBUF)]
+    del x0
     out = {}
     for n in (256, 1024, 4096):
         b = ELEMS // n
         row = {}
         with fftc.Plan(n, b, fftc.FORWARD, "c64") as p:
             row["stockham" + str(p.describe()["radices"])] = timer.avg_ms(
-                lambda i: p.execute(xs[i % 2], ys[i % 2], timer.s), 10) * 1e3
+                lambda i: p.execute(xs[i % NBUF], ys[i % NBUF], timer.s), 10) * 1e3
         for nn, order, radix in fftc.compiled_orders("c64"):
             if nn != n:
                 continue
             with fftc.plan_order(n, b, fftc.FORWARD, "c64", order, radix) as p:
                 row[f"{fftc.ORDER_NAMES[order]}_r{radix}"] = timer.avg_ms(
-                    lambda i: p.execute(xs[i % 2], ys[i % 2], timer.s), 10) * 1e3
+                    lambda i: p.execute(xs[i % NBUF], ys[i % NBUF], timer.s), 10) * 1e3
         res, best = fftc.autotune_orders(n, b, "c64", reps=5)
         out[str(n)] = {"us": row, "hbm_gbs": {k: 16.0 * ELEMS / (v * 1e-6) / 1e9 for k, v in row.items()},
                        "autotuner_pick": f"{res[best][0]}_r{res[best][1]}" if res[best][1] else res[best][0]}
