@@ -205,6 +205,7 @@ class Server {
         }
         incoming_.push_back(Pending{r, bytes});
         ++stats_.submitted;
+        wakes_.fetch_add(1, std::memory_order_release);
         cv_.notify_one();
         return FFTC_OK;
     }
@@ -226,6 +227,7 @@ class Server {
         arena_.release(it->second.first, it->second.second);
         live_.erase(it);
         stats_.bytes_in_use = arena_.used();
+        wakes_.fetch_add(1, std::memory_order_release);
         cv_.notify_one();
         return FFTC_OK;
     }
@@ -238,6 +240,7 @@ class Server {
             std::lock_guard<std::mutex> g(mu_);
             stop_ = true;
             drain_ = drain;
+            wakes_.fetch_add(1, std::memory_order_release);
             cv_.notify_one();
         }
         if (th_.joinable()) th_.join();
@@ -519,7 +522,19 @@ class Server {
                 if (stop_ && nrun == 0 && incoming_.empty() && pending_.empty()) break;
                 // idle, or the queue head waits for memory or a slot: sleep
                 // until a submit, release or stop (or a short timeout)
-                if (!progressed && nrun == 0) cv_.wait_for(lk, std::chrono::milliseconds(2));
+                if (!progressed && nrun == 0) {
+                    // idle: poll briefly for a submit, release or stop before
+                    // sleeping, so a request arriving soon after does not pay
+                    // for waking this thread
+                    const uint64_t seen = wakes_.load(std::memory_order_acquire);
+                    lk.unlock();
+                    const int64_t t0 = now_ns();
+                    while (wakes_.load(std::memory_order_acquire) == seen && now_ns() - t0 < kIdleSpinNs)
+                        std::this_thread::yield();
+                    lk.lock();
+                    if (wakes_.load(std::memory_order_acquire) == seen)
+                        cv_.wait_for(lk, std::chrono::milliseconds(2));
+                }
             }
             // work on the GPU: poll its events without a timed sleep
             if (!progressed && n_running() > 0) std::this_thread::yield();
@@ -546,6 +561,8 @@ class Server {
     std::vector<fftc_plan_t> retired_;
     fftc_server_stats stats_{};
     std::atomic<int64_t> fused_launches_{0}, fused_requests_{0};  // written by the dispatcher only
+    std::atomic<uint64_t> wakes_{0};  // submits, releases and stops, for the dispatcher's idle poll
+    static constexpr int64_t kIdleSpinNs = 100000;  // idle poll before sleeping: 100 us
 };
 
 std::mutex g_server_mu;
