@@ -181,6 +181,28 @@ def ptr(x) -> int:
     return int(x.data_ptr())
 
 
+def span_bytes(t) -> int:
+    """Bytes from a tensor's first to its last element (0 when empty)."""
+    if t.numel() == 0:
+        return 0
+    return (sum((n - 1) * st for n, st in zip(t.shape, t.stride())) + 1) * t.element_size()
+
+
+def check_extent(t, nbytes: int, what: str) -> None:
+    """Refuse a tensor smaller than what the launch would touch (integer
+    addresses are the caller's responsibility): the kernels cannot see a
+    buffer's size, and an access past its end faults the GPU."""
+    if t is None or isinstance(t, int):
+        return
+    try:
+        have = t.nbytes if t.is_contiguous() else span_bytes(t)
+    except AttributeError:  # not a tensor: an object with data_ptr() only
+        return
+    if have < nbytes:
+        raise FFTCError(1, f"{what} buffer",  # FFTC_ERR_INVALID_ARG
+                        f"{what} tensor spans {have} bytes, the plan touches {nbytes}")
+
+
 def stream_handle(stream) -> int:
     """hipStream_t of a torch stream, an int handle, or torch's current stream."""
     if stream is None:
@@ -224,12 +246,41 @@ class Plan:
     def handle(self) -> int:
         return self._h.value or 0
 
+    def bytes_needed(self) -> tuple:
+        """(input bytes, output bytes) one execute reads and writes, for the
+        whole batch; a layout side counts from its first to its last element
+        (per array when planar)."""
+        need = self.__dict__.get("_need")
+        if need is None:
+            d = self.describe()
+            cs = 16 if d["dtype"] == C128 else 8
+            if d["variant"] == "mixed_persistent":
+                need = (d["mixed_elements"] * cs,) * 2
+            elif d["has_layout"]:
+                def side(layout):
+                    stride, dist, planar = layout
+                    last = (d["batch"] - 1) * dist + (d["n"] - 1) * stride
+                    return (last + 1) * (cs // 2 if planar else cs)
+                need = (side(d["layout_in"]), side(d["layout_out"]))
+            else:
+                need = (d["n"] * d["batch"] * cs,) * 2
+            self._need = need
+            self._layout = bool(d["has_layout"])
+        return need
+
     def execute(self, x, y, stream=None) -> None:
         """Enqueue y = DFT(x) on the stream (default: torch's current stream)."""
+        nin, nout = self.bytes_needed()
+        check_extent(x, nin, "input")
+        check_extent(y, nout, "output")
         check(lib.fftc_execute(self._h, ptr(x), ptr(y), stream_handle(stream)), "fftc_execute")
 
     def execute_batch(self, x, y, batch: int, stream=None) -> None:
         """Enqueue the first `batch` transforms (1 <= batch <= the plan's batch)."""
+        nin, nout = self.bytes_needed()
+        if self.batch and 0 < int(batch) <= self.batch and not self._layout:
+            check_extent(x, nin * int(batch) // self.batch, "input")
+            check_extent(y, nout * int(batch) // self.batch, "output")
         check(lib.fftc_execute_batch(self._h, ptr(x), ptr(y), int(batch), stream_handle(stream)),
               "fftc_execute_batch")
 
@@ -326,6 +377,10 @@ def plan_layout(n: int, batch: int, direction: int = FORWARD, dtype="c64", in_la
 
 def execute_layout(plan: Plan, in_re, in_im, out_re, out_im, stream=None) -> None:
     """Run a layout plan: planar sides give (re, im), interleaved sides (array, None)."""
+    nin, nout = plan.bytes_needed()
+    for t, n, what in ((in_re, nin, "input"), (in_im, nin, "input (im)"), (out_re, nout, "output"),
+                       (out_im, nout, "output (im)")):
+        check_extent(t, n, what)
     check(lib.fftc_execute_layout(plan._h, ptr(in_re), ptr(in_im) or None, ptr(out_re), ptr(out_im) or None,
                                   stream_handle(stream)), "fftc_execute_layout")
 

@@ -197,3 +197,28 @@ def test_copy_reference():
     fftc.copy(x, y, 8 * (n - 1))  # 16-byte multiple: n - 1 elements
     torch.cuda.synchronize()
     assert torch.equal(y[:n - 1], x[:n - 1]) and not y[n - 1:].any()
+
+
+def test_undersized_tensors_refused_before_launch():
+    """The binding compares tensor extents with what a plan touches and
+    raises before anything is launched (the kernels cannot see sizes)."""
+    n, b = 1024, 4
+    x = torch.zeros(n * b - 1, dtype=torch.complex64, device="cuda")
+    y = torch.zeros(n * b, dtype=torch.complex64, device="cuda")
+    with fftc.Plan(n, b, FWD, "c64") as p:
+        assert p.bytes_needed() == (8 * n * b, 8 * n * b)
+        with pytest.raises(fftc.FFTCError) as e:
+            p.execute(x, y)
+        assert e.value.status == 1
+        with pytest.raises(fftc.FFTCError):
+            p.execute(y, x)
+        with pytest.raises(fftc.FFTCError):
+            p.execute_batch(y[: 2 * n - 1], y, 2)
+        p.execute_batch(y[: 2 * n], x[: 2 * n], 2)  # exactly large enough
+    # a planar layout with gaps: each array must reach the last element
+    with fftc.plan_layout(n, b, FWD, "c64", (1, n + 3, 1), None) as p:
+        assert p.bytes_needed() == (4 * ((b - 1) * (n + 3) + n), 8 * n * b)
+        re = torch.zeros((b - 1) * (n + 3) + n - 1, device="cuda")
+        with pytest.raises(fftc.FFTCError):
+            fftc.execute_layout(p, re, re, y, None)
+    torch.cuda.synchronize()
