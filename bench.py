@@ -344,9 +344,15 @@ def config4(torch, fftc, synth, timer):
         refn = ref.view(b, n)
         refnorm = torch.linalg.vector_norm(refn, dim=1)
         row = {"c128_us": ms128 * 1e3}
+        # rotating copies of the input (at least 512 MiB read per cycle where
+        # memory allows) so the timed launches stream from HBM
+        nb = max(2, min(4, (1 << 30) // (8 * b * n)))
+        xs = [x] + [x.clone() for _ in range(nb - 1)]
+        ys = [y] + [torch.empty_like(y) for _ in range(nb - 1)]
         for mode in modes:
             with fftc.Plan(n, b, fftc.FORWARD, mode) as p:
-                ms = timer.avg_ms(lambda i: p.execute(x, y, timer.s), 5)
+                ms = timer.avg_ms(lambda i: p.execute(xs[i % nb], ys[i % nb], timer.s), 5)
+                p.execute(x, y, timer.s)
                 torch.cuda.synchronize()
                 err = (torch.linalg.vector_norm(y.view(b, n).to(torch.complex128) - refn, dim=1) / refnorm)
                 e = {"us": ms * 1e3, "gflops": flops(n, b) / (ms * 1e-3) / 1e9,
@@ -363,8 +369,9 @@ def config4(torch, fftc, synth, timer):
                     e["mfma_tflops"] = mf / (ms * 1e-3) / 1e12
                     e["mfma_util"] = e["mfma_tflops"] / MFMA_PEAK_TFLOPS["f16"]
                 row[mode] = e
+        row["rotating_buffers"] = nb
         out[str(n)] = row
-        del x, y, ref, refn
+        del x, y, xs, ys, ref, refn
         torch.cuda.empty_cache()
     return {"workload": "forward complex64, batch 8192, Gaussian(0,1) inputs; error = relative L2 "
                         "per transform against the complex128 GPU path", "by_n": out}
