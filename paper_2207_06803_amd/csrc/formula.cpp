@@ -108,7 +108,9 @@ struct Parser {
         return 0;
     }
     // After a matrix product: an identifier that is no keyword, followed by
-    // the end of the text, is the vector operand.
+    // the end of the text, is the vector operand. The word form of the
+    // Kronecker product is a keyword too, so 'DFT(2) . kron' is an operator
+    // with no right operand, not a product with a vector named 'kron'.
     bool trailing_operand() {
         ws();
         size_t j = i;
@@ -116,7 +118,8 @@ struct Parser {
         while (j < s.size() && idch(s[j])) ++j;
         std::string w;
         for (size_t k = i; k < j; ++k) w += (char)tolower((unsigned char)s[k]);
-        if (w == "dft" || w == "i" || w == "identity" || w == "twiddle" || w == "permute") return false;
+        if (w == "dft" || w == "i" || w == "identity" || w == "twiddle" || w == "permute" || w == "kron")
+            return false;
         size_t e = j;
         while (e < s.size() && isspace((unsigned char)s[e])) ++e;
         if (e != s.size()) return false;

@@ -181,26 +181,41 @@ def ptr(x) -> int:
     return int(x.data_ptr())
 
 
-def span_bytes(t) -> int:
-    """Bytes from a tensor's first to its last element (0 when empty)."""
-    if t.numel() == 0:
-        return 0
-    return (sum((n - 1) * st for n, st in zip(t.shape, t.stride())) + 1) * t.element_size()
-
-
-def check_extent(t, nbytes: int, what: str) -> None:
-    """Refuse a tensor smaller than what the launch would touch (integer
-    addresses are the caller's responsibility): the kernels cannot see a
-    buffer's size, and an access past its end faults the GPU."""
+def check_extent(t, nbytes: int, what: str, device=None) -> None:
+    """Refuse a tensor the kernels cannot use as a dense device buffer of at
+    least `nbytes` (integer addresses are the caller's responsibility): a host
+    tensor, one on another GPU than the plan's, a non-contiguous view (the
+    kernels ignore torch strides and would read and write the storage between
+    its elements), or one smaller than what the launch touches (the kernels
+    cannot see a buffer's size, and an access past its end faults the GPU)."""
     if t is None or isinstance(t, int):
         return
+    dev = getattr(t, "device", None)
+    if dev is not None:
+        if getattr(dev, "type", "cuda") != "cuda":
+            raise FFTCError(1, f"{what} buffer", f"{what} tensor is on {dev}, not on a GPU")
+        if device is not None and dev.index is not None and dev.index != device:
+            raise FFTCError(1, f"{what} buffer", f"{what} tensor is on {dev}, the plan on cuda:{device}")
     try:
-        have = t.nbytes if t.is_contiguous() else span_bytes(t)
+        contiguous = t.is_contiguous()
+        have = t.nbytes
     except AttributeError:  # not a tensor: an object with data_ptr() only
         return
+    if not contiguous:
+        raise FFTCError(1, f"{what} buffer", f"{what} tensor is a non-contiguous view")
     if have < nbytes:
         raise FFTCError(1, f"{what} buffer",  # FFTC_ERR_INVALID_ARG
                         f"{what} tensor spans {have} bytes, the plan touches {nbytes}")
+
+
+def _current_device():
+    """Index of the GPU plans are created on (HIP's current device, which
+    torch's current device sets), or None without a usable torch."""
+    try:
+        import torch
+        return int(torch.cuda.current_device()) if torch.cuda.is_available() else None
+    except Exception:
+        return None
 
 
 def stream_handle(stream) -> int:
@@ -228,6 +243,7 @@ class Plan:
     def __init__(self, n: int, batch: int, direction: int = FORWARD, dtype="c64", radices=None,
                  _handle=None):
         code = dtype_code(dtype)
+        self.device = _current_device()
         if _handle is not None:
             self._h = _handle
             self.n, self.batch, self.direction, self.dtype = n, batch, direction, code
@@ -246,41 +262,41 @@ class Plan:
     def handle(self) -> int:
         return self._h.value or 0
 
-    def bytes_needed(self) -> tuple:
-        """(input bytes, output bytes) one execute reads and writes, for the
-        whole batch; a layout side counts from its first to its last element
-        (per array when planar)."""
-        need = self.__dict__.get("_need")
-        if need is None:
-            d = self.describe()
-            cs = 16 if d["dtype"] == C128 else 8
-            if d["variant"] == "mixed_persistent":
-                need = (d["mixed_elements"] * cs,) * 2
-            elif d["has_layout"]:
-                def side(layout):
-                    stride, dist, planar = layout
-                    last = (d["batch"] - 1) * dist + (d["n"] - 1) * stride
-                    return (last + 1) * (cs // 2 if planar else cs)
-                need = (side(d["layout_in"]), side(d["layout_out"]))
-            else:
-                need = (d["n"] * d["batch"] * cs,) * 2
-            self._need = need
-            self._layout = bool(d["has_layout"])
-        return need
+    def bytes_needed(self, batch=None) -> tuple:
+        """(input bytes, output bytes) one execute of the first `batch`
+        transforms (default: the plan's batch) reads and writes; a layout side
+        counts from its first to its last element (per array when planar)."""
+        d = self.__dict__.get("_desc")
+        if d is None:
+            d = self._desc = self.describe()
+        cs = 16 if d["dtype"] == C128 else 8
+        if d["variant"] == "mixed_persistent":
+            return (d["mixed_elements"] * cs,) * 2
+        b = d["batch"] if batch is None else int(batch)
+        if b <= 0:
+            return (0, 0)
+        if d["has_layout"]:
+            def side(layout):
+                stride, dist, planar = layout
+                last = (b - 1) * dist + (d["n"] - 1) * stride
+                return (last + 1) * (cs // 2 if planar else cs)
+            return (side(d["layout_in"]), side(d["layout_out"]))
+        return (d["n"] * b * cs,) * 2
 
     def execute(self, x, y, stream=None) -> None:
         """Enqueue y = DFT(x) on the stream (default: torch's current stream)."""
         nin, nout = self.bytes_needed()
-        check_extent(x, nin, "input")
-        check_extent(y, nout, "output")
+        check_extent(x, nin, "input", self.device)
+        check_extent(y, nout, "output", self.device)
         check(lib.fftc_execute(self._h, ptr(x), ptr(y), stream_handle(stream)), "fftc_execute")
 
     def execute_batch(self, x, y, batch: int, stream=None) -> None:
-        """Enqueue the first `batch` transforms (1 <= batch <= the plan's batch)."""
-        nin, nout = self.bytes_needed()
-        if self.batch and 0 < int(batch) <= self.batch and not self._layout:
-            check_extent(x, nin * int(batch) // self.batch, "input")
-            check_extent(y, nout * int(batch) // self.batch, "output")
+        """Enqueue the first `batch` transforms (1 <= batch <= the plan's batch;
+        the library refuses any other count before touching memory)."""
+        if self.batch and 0 < int(batch) <= self.batch:
+            nin, nout = self.bytes_needed(batch)
+            check_extent(x, nin, "input", self.device)
+            check_extent(y, nout, "output", self.device)
         check(lib.fftc_execute_batch(self._h, ptr(x), ptr(y), int(batch), stream_handle(stream)),
               "fftc_execute_batch")
 
@@ -380,7 +396,7 @@ def execute_layout(plan: Plan, in_re, in_im, out_re, out_im, stream=None) -> Non
     nin, nout = plan.bytes_needed()
     for t, n, what in ((in_re, nin, "input"), (in_im, nin, "input (im)"), (out_re, nout, "output"),
                        (out_im, nout, "output (im)")):
-        check_extent(t, n, what)
+        check_extent(t, n, what, plan.device)
     check(lib.fftc_execute_layout(plan._h, ptr(in_re), ptr(in_im) or None, ptr(out_re), ptr(out_im) or None,
                                   stream_handle(stream)), "fftc_execute_layout")
 
@@ -477,6 +493,8 @@ def compiled_lists(dtype="c64"):
 def copy(x, y, nbytes: int, stream=None) -> None:
     """Device copy of nbytes from x to y with 16-byte nontemporal accesses
     (the library's bandwidth reference)."""
+    check_extent(x, int(nbytes), "copy source")
+    check_extent(y, int(nbytes), "copy destination")
     check(lib.fftc_copy(ptr(x), ptr(y), int(nbytes), stream_handle(stream)), "fftc_copy")
 
 

@@ -127,3 +127,31 @@ def test_compiled_lists_multiply_to_dft_small():
     for n, rs in fftc.compiled_lists("c64"):
         if n <= 128:
             assert np.abs(F.stockham_product(n, rs) - F.dft_matrix(n)).max() < 1e-11, (n, rs)
+
+
+def test_binding_refuses_host_and_strided_tensors():
+    """The binding's buffer checks run before any library call: a host tensor
+    and a non-contiguous device view are refused (the kernels would take a host
+    address, or ignore the view's strides)."""
+    import torch
+
+    class FakeDeviceTensor:  # a device view as far as the checks can see
+        def __init__(self, contiguous, nbytes, index=0):
+            self.device = torch.device("cuda", index)
+            self._c, self.nbytes = contiguous, nbytes
+
+        def is_contiguous(self):
+            return self._c
+
+    with pytest.raises(fftc.FFTCError) as e:
+        fftc.check_extent(torch.zeros(16, dtype=torch.complex64), 128, "input")
+    assert e.value.status == 1 and "not on a GPU" in str(e.value)
+    with pytest.raises(fftc.FFTCError):
+        fftc.check_extent(FakeDeviceTensor(False, 1 << 20), 128, "input")
+    with pytest.raises(fftc.FFTCError):
+        fftc.check_extent(FakeDeviceTensor(True, 120), 128, "input")
+    with pytest.raises(fftc.FFTCError):
+        fftc.check_extent(FakeDeviceTensor(True, 128, index=1), 128, "input", device=0)
+    fftc.check_extent(FakeDeviceTensor(True, 128), 128, "input", device=0)
+    with pytest.raises(fftc.FFTCError):
+        fftc.copy(torch.zeros(4, dtype=torch.complex64), torch.zeros(4, dtype=torch.complex64), 32)

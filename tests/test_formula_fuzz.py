@@ -94,3 +94,19 @@ def test_random_formulas_lower_to_the_oracle(f, flags):
     else:
         got = replay(desc, x)
     assert np.abs(got - want).max() < 1e-10 * max(1, n), (text, desc)
+
+
+# texts the token soup has drawn where the two parsers once disagreed; each
+# must be judged the same way by both, every run
+@pytest.mark.parametrize("text", [
+    "DFT(2)· kron ",            # the word form of the Kronecker product is no vector name
+    "DFT(2) . KRON",
+    "DFT(2) · kron_x",          # an identifier that only starts with the keyword is a vector
+    "DFT(4) · Input",
+])
+def test_parsers_agree_on_recorded_cases(text):
+    ok_lib, v_lib = lib_result(text)
+    ok_or, v_or = oracle_result(text)
+    assert ok_lib == ok_or, (text, ok_lib, ok_or)
+    if ok_lib:
+        assert v_lib == v_or, text

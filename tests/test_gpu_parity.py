@@ -222,3 +222,32 @@ def test_undersized_tensors_refused_before_launch():
         with pytest.raises(fftc.FFTCError):
             fftc.execute_layout(p, re, re, y, None)
     torch.cuda.synchronize()
+
+
+def test_unusable_tensors_refused_before_launch():
+    """Host tensors, non-contiguous views, under-sized batch slices of a
+    layout plan and under-sized copy operands raise before any launch."""
+    n, b = 256, 4
+    y = torch.zeros(n * b, dtype=torch.complex64, device="cuda")
+    big = torch.zeros(2 * n * b, dtype=torch.complex64, device="cuda")
+    with fftc.Plan(n, b, FWD, "c64") as p:
+        with pytest.raises(fftc.FFTCError) as e:
+            p.execute(torch.zeros(n * b, dtype=torch.complex64), y)       # host memory
+        assert e.value.status == 1
+        with pytest.raises(fftc.FFTCError):
+            p.execute(big[::2], y)                                           # spans enough, not dense
+        with pytest.raises(fftc.FFTCError):
+            p.execute_batch(y, big.view(2, n * b).t(), 1)                 # transposed view
+    # layout plan: each batch slice must reach its own last element
+    lay = (1, n + 8, 0)
+    with fftc.plan_layout(n, b, FWD, "c64", lay, lay) as p:
+        need2 = (2 - 1) * (n + 8) + n
+        assert p.bytes_needed(2) == (8 * need2, 8 * need2)
+        with pytest.raises(fftc.FFTCError):
+            p.execute_batch(big[: need2 - 1], big[: need2], 2)
+        p.execute_batch(y[: need2], big[: need2], 2)
+    with pytest.raises(fftc.FFTCError):
+        fftc.copy(y[: n - 2], big, 8 * n)                                    # source too short
+    with pytest.raises(fftc.FFTCError):
+        fftc.copy(big, y[: n - 2], 8 * n)                                    # destination too short
+    torch.cuda.synchronize()
