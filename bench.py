@@ -17,7 +17,8 @@ HIP events on the stream its kernels run on):
   * 10,000 mixed-length transforms: one persistent launch (hipGraph) vs the
     per-length path (37 batched launches, graph-captured)
   * split-precision MFMA modes at N = 1024, 4096, 16384, batch 8192: time and
-    error against the complex128 GPU path
+    error against the FP64 oracle on 256 sampled transforms per N (computed in
+    the CPU-baseline leg) and against the complex128 GPU path
   * serving: 20,000 Poisson-arriving requests, p50/p99 latency, with and
     without fusing same-length requests into one launch, at the configured
     rate and at four times it, and a sweep of the arrival rate (1x to 32x)
@@ -323,6 +324,20 @@ def config3(torch, fftc, synth, timer):
             "autotune_s": tune_s, "tuned_lists": {str(k): v for k, v in tuned.items()}}
 
 
+# Sampled inputs and outputs of the precision study, checked against the FP64
+# oracle in the CPU-baseline leg (the only part of the benchmark that runs the
+# oracle): [(n, rows, host input rows, {path: host output rows}, result row)]
+PRECISION_SAMPLES = []
+PRECISION_SAMPLE_ROWS = 256
+
+
+def precision_rows(synth, n, b):
+    """A seeded sample of transforms of a batch, always with the first and the last."""
+    g = synth.rng(4, n, 99)
+    rest = g.choice(np.arange(1, b - 1), size=min(b - 2, PRECISION_SAMPLE_ROWS - 2), replace=False)
+    return np.unique(np.concatenate([[0, b - 1], rest])).astype(np.int64)
+
+
 def config4(torch, fftc, synth, timer):
     out = {}
     modes = ("c64", "split_f16", "split_bf16", "split3_bf16", "f16")
@@ -330,10 +345,13 @@ def config4(torch, fftc, synth, timer):
     for n in (1024, 4096, 16384):
         b = 8192
         xh = synth.gaussian_complex(synth.rng(4, n), (b * n,), np.complex64)
+        rows = precision_rows(synth, n, b)
+        x_rows = xh.reshape(b, n)[rows].copy()
         x = torch.from_numpy(xh).to("cuda")
         del xh
+        rows_d = torch.from_numpy(rows).to("cuda")
         y = torch.empty_like(x)
-        # reference: the complex128 GPU path on the same (upcast) input
+        # complex128 GPU path on the same (upcast) input
         x128 = x.to(torch.complex128)
         ref = torch.empty_like(x128)
         with fftc.Plan(n, b, fftc.FORWARD, "c128") as p:
@@ -343,7 +361,8 @@ def config4(torch, fftc, synth, timer):
         del x128
         refn = ref.view(b, n)
         refnorm = torch.linalg.vector_norm(refn, dim=1)
-        row = {"c128_us": ms128 * 1e3}
+        outs = {"c128": refn.index_select(0, rows_d).cpu().numpy()}
+        row = {"c128": {"us": ms128 * 1e3}}
         # rotating copies of the input (at least 512 MiB read per cycle where
         # memory allows) so the timed launches stream from HBM
         nb = max(2, min(4, (1 << 30) // (8 * b * n)))
@@ -354,10 +373,12 @@ def config4(torch, fftc, synth, timer):
                 ms = timer.avg_ms(lambda i: p.execute(xs[i % nb], ys[i % nb], timer.s), 5)
                 p.execute(x, y, timer.s)
                 torch.cuda.synchronize()
-                err = (torch.linalg.vector_norm(y.view(b, n).to(torch.complex128) - refn, dim=1) / refnorm)
+                yv = y.view(b, n)
+                err = (torch.linalg.vector_norm(yv.to(torch.complex128) - refn, dim=1) / refnorm)
+                outs[mode] = yv.index_select(0, rows_d).cpu().numpy()
                 e = {"us": ms * 1e3, "gflops": flops(n, b) / (ms * 1e-3) / 1e9,
                      "hbm_gbs": 16.0 * n * b / (ms * 1e-3) / 1e9,
-                     "rel_l2_max": float(err.max()), "rel_l2_mean": float(err.mean())}
+                     "rel_l2_vs_c128_max": float(err.max()), "rel_l2_vs_c128_mean": float(err.mean())}
                 if mode in mfma_per_group:
                     s16 = 0
                     m = n
@@ -370,11 +391,34 @@ def config4(torch, fftc, synth, timer):
                     e["mfma_util"] = e["mfma_tflops"] / MFMA_PEAK_TFLOPS["f16"]
                 row[mode] = e
         row["rotating_buffers"] = nb
+        row["oracle_sample_rows"] = int(len(rows))
         out[str(n)] = row
+        PRECISION_SAMPLES.append((n, rows, x_rows, outs, row))
         del x, y, xs, ys, ref, refn
         torch.cuda.empty_cache()
     return {"workload": "forward complex64, batch 8192, Gaussian(0,1) inputs; error = relative L2 "
-                        "per transform against the complex128 GPU path", "by_n": out}
+                        "per transform against the FP64 oracle on a seeded sample of 256 transforms "
+                        "(always the first and the last; filled in by the CPU-baseline leg) and "
+                        "against the complex128 GPU path over the whole batch", "by_n": out}
+
+
+def oracle_precision(oracle):
+    """The FP64 oracle on the precision study's sampled inputs: every path's
+    relative L2 error per sampled transform (max and mean), written into the
+    study's rows; returns the oracle's time on these samples."""
+    t_all, done = 0.0, []
+    for n, rows, x_rows, outs, row in PRECISION_SAMPLES:
+        t0 = time.perf_counter()
+        want = oracle.dft(x_rows, -1)
+        t_all += time.perf_counter() - t0
+        den = np.linalg.norm(want, axis=1)
+        for path, got in outs.items():
+            err = np.linalg.norm(got.astype(np.complex128) - want, axis=1) / den
+            row[path]["rel_l2_vs_oracle_max"] = float(err.max())
+            row[path]["rel_l2_vs_oracle_mean"] = float(err.mean())
+        done.append(f"{n}:{len(rows)}")
+    PRECISION_SAMPLES.clear()
+    return {"transforms": ", ".join(done), "seconds": t_all}
 
 
 def copy_ceiling(torch, fftc, synth, timer):
@@ -615,8 +659,10 @@ def serving_sweep(args, torch, fftc, synth):
 
 def cpu_baseline(seconds):
     """The FP64 O(N^2) oracle on the host cores, on a bounded sample of the
-    headline workload (transforms of each N, both directions)."""
+    headline workload (transforms of each N, both directions); also the
+    oracle's reference values for the precision study's sampled transforms."""
     import oracle
+    precision = oracle_precision(oracle) if PRECISION_SAMPLES else None
     from paper_2207_06803_amd import synth
     threads = oracle.max_threads()
     g = synth.rng(1, 77)
@@ -651,7 +697,8 @@ def cpu_baseline(seconds):
                       + ", ".join(f"{n}:{c}" for n, c in counts.items()) + f" ({tot_t:.1f} s)",
             "transforms_per_s": {str(n): r for n, r in rate.items()},
             "one_core": {"sample": "64 forward transforms of N = 1024", "transforms_per_s": 64 / t1,
-                         "gflops": flops(1024, 64) / t1 / 1e9}}
+                         "gflops": flops(1024, 64) / t1 / 1e9},
+            "precision_study_oracle": precision}
 
 
 def rocpd_summary(paths):

@@ -69,3 +69,30 @@ def test_split_unsupported_lengths():
         with pytest.raises(fftc.FFTCError) as e:
             fftc.Plan(n, 1, fftc.FORWARD, "split_f16")
         assert e.value.status == 2
+
+
+@pytest.mark.parametrize("n", [1024, 4096, 16384])
+def test_split_modes_at_benchmark_batch(n):
+    """Batch 8192, the precision study's launch: the study's Gaussian input,
+    every mode, checked on sampled transforms (always the first and the last)
+    against the FP64 oracle."""
+    b = 8192
+    x = synth.gaussian_complex(synth.rng(4, n), (b * n,), np.complex64)
+    g = synth.rng(4, n, 98)
+    rows = np.unique(np.concatenate([[0, 1, b // 2, b - 1], g.choice(b, 4, replace=False)]))
+    ref = oracle.dft(x.reshape(b, n)[rows])
+    xd = torch.from_numpy(x).to("cuda")
+    del x
+    yd = torch.empty_like(xd)
+    rows_d = torch.from_numpy(rows).to("cuda")
+    for mode in sorted(BOUNDS):
+        say(f"{mode} n={n} batch={b}")
+        with fftc.Plan(n, b, fftc.FORWARD, mode) as p:
+            p.execute(xd, yd)
+            torch.cuda.synchronize()
+        got = yd.view(b, n).index_select(0, rows_d).cpu().numpy()
+        err = rel_l2(got, ref)
+        say(f"  sampled rows {rows.tolist()}: max rel L2 {err.max():.3e} mean {err.mean():.3e}")
+        assert err.max() <= BOUNDS[mode], (mode, n, err.max())
+    del xd, yd
+    torch.cuda.empty_cache()
