@@ -108,6 +108,32 @@ fftc_status fftc_execute(fftc_plan_t plan, const void *in, void *out, void *stre
  * plan's batch); in and out hold batch * n elements.  Not for mixed plans. */
 fftc_status fftc_execute_batch(fftc_plan_t plan, const void *in, void *out, int64_t batch, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): plan and
+ * run `batch` transforms of length n in one call, as fftc_plan (without a
+ * recorded alternative order or an explicit radix list) followed by
+ * fftc_execute, with no hipMalloc, hipFree or other device allocation.
+ *   dtype: FFTC_C64 or FFTC_C128 only; n, batch, direction, in, out, stream
+ *   as for fftc_plan / fftc_execute (in == out allowed, other overlaps not).
+ * The twiddle tables (made in fp64 on the GPU by a kernel enqueued on
+ * `stream`) and, for an in-place call of a two-pass length, the intermediate
+ * live in one static device array of fftc_static_scratch_bytes() bytes (64
+ * MiB) that each GPU the library runs on holds until the process ends: 2 MiB
+ * for tables, the rest for the intermediate, which an in-place call fills a
+ * chunk of transforms at a time.  Lengths whose tables exceed 2 MiB give
+ * FFTC_ERR_TOO_LARGE (none of the supported lengths does).  Asynchronous;
+ * results equal fftc_plan + fftc_execute's bit for bit.  Every call on one
+ * GPU shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and give wrong results; calls ordered on one
+ * stream are safe.
+ */
+fftc_status fftc_execute_static(int64_t n, int64_t batch, int direction, int dtype, const void *in, void *out,
+                                void *stream);
+
+/* Size in bytes of fftc_execute_static's static device array. */
+size_t fftc_static_scratch_bytes(void);
+
 /* ---------------------------------------------------------------------------
  * Data layouts (planar and strided).  The DSL of the paper's Section IV-A
  * builds its complex input from separate real and imaginary arrays

@@ -124,11 +124,10 @@ static fftc_status plan_order_impl(int64_t n, int64_t batch, int direction, int 
     return FFTC_OK;
 }
 
-static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype, const int* radices,
-                             int count, fftc_plan_t* out) {
-    clear_error();
-    if (!out) return fail(FFTC_ERR_INVALID_ARG, "plan_out is NULL");
-    *out = nullptr;
+// Argument checks shared by fftc_plan, fftc_plan_radices and
+// fftc_execute_static; nothing touches the device.
+static fftc_status check_plan_args(int64_t n, int64_t batch, int direction, int dtype, const int* radices,
+                                   int count) {
     if (direction != FFTC_FORWARD && direction != FFTC_INVERSE)
         return fail(FFTC_ERR_INVALID_ARG, "direction must be FFTC_FORWARD (-1) or FFTC_INVERSE (+1)");
     if (dtype != FFTC_C64 && dtype != FFTC_C128 && !is_split_dtype(dtype))
@@ -146,12 +145,103 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
     if (batch > (int64_t(1) << 40) / n) return fail(FFTC_ERR_INVALID_ARG, "batch * n too large");
     if (radices && n > max_single_n(dtype))
         return fail(FFTC_ERR_INVALID_ARG, "explicit radix lists are for single-kernel lengths only");
-    if (radices) {  // validate before touching the device
+    if (radices) {
         if (count < 0 || count > kMaxStages || (count == 0 && n != 1))
             return fail(FFTC_ERR_INVALID_ARG, "bad radix count");
         fftc_status cr = check_radices(n, std::vector<int>(radices, radices + count));
         if (cr != FFTC_OK) return cr;
     }
+    return FFTC_OK;
+}
+
+// Everything a Stockham, two-pass or split plan holds except device memory:
+// radix lists, variant, launch shape, table offsets, and the twiddle
+// segments its table needs (*entries elements in all).
+fftc_status shape_plan(fftc_plan_s* p, const int* radices, int count, std::vector<TwSegment>* segs,
+                       int64_t* entries) {
+    const int64_t n = p->n;
+    const int dtype = p->dtype;
+    const size_t cs = csize_of(dtype);
+    segs->clear();
+    *entries = 0;
+    if (is_split_dtype(dtype)) {
+        p->variant = FFTC_VARIANT_SPLIT_MFMA;
+        p->radices = split_radices(n);
+        p->tpt = split_threads(n);
+        p->t = 1;
+        *entries = stage_segments(p->radices, 0, segs);
+        return FFTC_OK;
+    }
+    if (n <= max_single_n(dtype)) {
+        std::vector<int> rs;
+        if (radices) {
+            rs.assign(radices, radices + count);
+        } else {
+            rs = choose_radices(n, dtype);
+        }
+        // DFT_1 is the identity: an empty radix list (the kernel copies)
+        if (n == 1) rs.clear();
+        if (n > 1 && rs.empty()) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no factorisation");
+        fftc_status st = shape_single(p, rs);
+        if (st != FFTC_OK) return st;
+        *entries = stage_segments(rs, 0, segs);
+        return FFTC_OK;
+    }
+    int64_t m = 0, k = 0;
+    if (!two_pass_split(n, dtype, &m, &k)) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no two-pass split");
+    p->variant = FFTC_VARIANT_TWO_PASS;
+    p->m = m;
+    p->k = k;
+    // prefer a column list with compiled kernels: the tuned or preferred
+    // list, else the planner's first candidate
+    auto pick = [&](int64_t len, const FourStepEntry** fs) {
+        std::vector<int> rs = choose_radices(len, dtype);
+        *fs = find_fourstep(dtype, len, rs);
+        if (!*fs) {
+            auto c = radix_candidates(len, 1);
+            if (!c.empty() && (*fs = find_fourstep(dtype, len, c[0])) != nullptr) rs = c[0];
+        }
+        return rs;
+    };
+    p->r1 = pick(m, &p->fs1);
+    p->r2 = pick(k, &p->fs2);
+    const int tc = two_pass_cols(dtype);
+    // columns per pass-1 tile (the compiled kernel's own width)
+    const int tc1 = p->fs1 ? p->fs1->tc : tc;
+    int tpt1, tpt2, tdummy;
+    launch_shape(m, p->r1, (int)cs, &tpt1, &tdummy);
+    launch_shape(k, p->r2, (int)cs, &tpt2, &tdummy);
+    if (tpt1 * tc > 1024 || tpt2 * tc > 1024 ||
+        (size_t)tc * tile_pitch((int)std::max(m, k)) * cs > (size_t)kLdsMaxPerGroup)
+        return fail(FFTC_ERR_UNSUPPORTED_SIZE, "two-pass tile does not fit a workgroup");
+    p->tw1_off = 0;
+    const int64_t e1 = stage_segments(p->r1, 0, segs);
+    p->tw2_off = e1;
+    const int64_t e2 = stage_segments(p->r2, e1, segs);
+    p->twn_off = e1 + e2;
+    // w_N^e for e < N as fine (e mod 1024) x coarse (e div 1024) tables
+    const int64_t nhi = (n + kTwSplit - 1) / kTwSplit;
+    segs->push_back({p->twn_off, kTwSplit, kTwSplit, n, 1});
+    segs->push_back({p->twn_off + kTwSplit, nhi, nhi, n, kTwSplit});
+    // then w_N^{c p} at [c M + p] for the c < tc1 columns of a tile
+    segs->push_back({p->twn_off + kTwSplit + nhi, tc1 * m, m, n, 1, 0});
+    fill_gen_desc(m, p->r1, tpt1, tc, p->tw1_off, &p->pass1);
+    fill_gen_desc(k, p->r2, tpt2, tc, p->tw2_off, &p->pass2);
+    p->radices = p->r1;
+    p->radices.insert(p->radices.end(), p->r2.begin(), p->r2.end());
+    p->tpt = tpt1;
+    p->t = tc;
+    *entries = p->twn_off + kTwSplit + nhi + tc1 * m;
+    return FFTC_OK;
+}
+
+static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype, const int* radices,
+                             int count, fftc_plan_t* out) {
+    clear_error();
+    if (!out) return fail(FFTC_ERR_INVALID_ARG, "plan_out is NULL");
+    *out = nullptr;
+    fftc_status st = check_plan_args(n, batch, direction, dtype, radices, count);
+    if (st != FFTC_OK) return st;
     if (!radices && !is_split_dtype(dtype)) {  // an alternative order the order autotuner recorded
         int order = 0, radix = 0;
         const OrderEntry* o = nullptr;
@@ -159,7 +249,7 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
             batch <= (int64_t(1) << 31))
             return plan_order_impl(n, batch, direction, dtype, o, out);
     }
-    fftc_status st = enable_large_lds();
+    st = enable_large_lds();
     if (st != FFTC_OK) return st;
 
     fftc_plan_s* p = new (std::nothrow) fftc_plan_s();
@@ -173,88 +263,14 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
         delete p;
         return fail_hip(de, "hipGetDevice");
     }
-    const size_t cs = csize_of(dtype);
-
-    if (is_split_dtype(dtype)) {
-        p->variant = FFTC_VARIANT_SPLIT_MFMA;
-        p->radices = split_radices(n);
-        p->tpt = split_threads(n);
-        p->t = 1;
-        std::vector<TwSegment> segs;
-        const int64_t entries = stage_segments(p->radices, 0, &segs);
-        st = alloc_tables(p, segs, entries);
-    } else if (n <= max_single_n(dtype)) {
-        std::vector<int> rs;
-        if (radices) {
-            rs.assign(radices, radices + count);
-        } else {
-            rs = choose_radices(n, dtype);
-        }
-        // DFT_1 is the identity: an empty radix list (the kernel copies)
-        if (st == FFTC_OK && n == 1) rs.clear();
-        if (st == FFTC_OK && n > 1 && rs.empty()) st = fail(FFTC_ERR_UNSUPPORTED_SIZE, "no factorisation");
-        if (st == FFTC_OK) st = shape_single(p, rs);
-        if (st == FFTC_OK) {
-            std::vector<TwSegment> segs;
-            const int64_t entries = stage_segments(rs, 0, &segs);
-            st = alloc_tables(p, segs, entries);
-        }
-    } else {
-        int64_t m = 0, k = 0;
-        if (!two_pass_split(n, dtype, &m, &k)) st = fail(FFTC_ERR_UNSUPPORTED_SIZE, "no two-pass split");
-        if (st == FFTC_OK) {
-            p->variant = FFTC_VARIANT_TWO_PASS;
-            p->m = m;
-            p->k = k;
-            // prefer a column list with compiled kernels: the tuned or
-            // preferred list, else the planner's first candidate
-            auto pick = [&](int64_t len, const FourStepEntry** fs) {
-                std::vector<int> rs = choose_radices(len, dtype);
-                *fs = find_fourstep(dtype, len, rs);
-                if (!*fs) {
-                    auto c = radix_candidates(len, 1);
-                    if (!c.empty() && (*fs = find_fourstep(dtype, len, c[0])) != nullptr) rs = c[0];
-                }
-                return rs;
-            };
-            p->r1 = pick(m, &p->fs1);
-            p->r2 = pick(k, &p->fs2);
-            const int tc = two_pass_cols(dtype);
-            // columns per pass-1 tile (the compiled kernel's own width)
-            const int tc1 = p->fs1 ? p->fs1->tc : tc;
-            int tpt1, tpt2, tdummy;
-            launch_shape(m, p->r1, (int)cs, &tpt1, &tdummy);
-            launch_shape(k, p->r2, (int)cs, &tpt2, &tdummy);
-            if (tpt1 * tc > 1024 || tpt2 * tc > 1024 ||
-                (size_t)tc * tile_pitch((int)std::max(m, k)) * cs > (size_t)kLdsMaxPerGroup)
-                st = fail(FFTC_ERR_UNSUPPORTED_SIZE, "two-pass tile does not fit a workgroup");
-            if (st == FFTC_OK) {
-                std::vector<TwSegment> segs;
-                p->tw1_off = 0;
-                const int64_t e1 = stage_segments(p->r1, 0, &segs);
-                p->tw2_off = e1;
-                const int64_t e2 = stage_segments(p->r2, e1, &segs);
-                p->twn_off = e1 + e2;
-                // w_N^e for e < N as fine (e mod 1024) x coarse (e div 1024) tables
-                const int64_t nhi = (n + kTwSplit - 1) / kTwSplit;
-                segs.push_back({p->twn_off, kTwSplit, kTwSplit, n, 1});
-                segs.push_back({p->twn_off + kTwSplit, nhi, nhi, n, kTwSplit});
-                // then w_N^{c p} at [c M + p] for the c < tc1 columns of a tile
-                segs.push_back({p->twn_off + kTwSplit + nhi, tc1 * m, m, n, 1, 0});
-                fill_gen_desc(m, p->r1, tpt1, tc, p->tw1_off, &p->pass1);
-                fill_gen_desc(k, p->r2, tpt2, tc, p->tw2_off, &p->pass2);
-                p->radices = p->r1;
-                p->radices.insert(p->radices.end(), p->r2.begin(), p->r2.end());
-                p->tpt = tpt1;
-                p->t = tc;
-                st = alloc_tables(p, segs, p->twn_off + kTwSplit + nhi + tc1 * m);
-            }
-            if (st == FFTC_OK && !t_plan_no_scratch) {
-                p->scratch_bytes = (size_t)batch * (size_t)n * cs;
-                hipError_t e = hipMalloc(&p->scratch, p->scratch_bytes);
-                if (e != hipSuccess) st = fail_hip(e, "hipMalloc(two-pass scratch)");
-            }
-        }
+    std::vector<TwSegment> segs;
+    int64_t entries = 0;
+    st = shape_plan(p, radices, count, &segs, &entries);
+    if (st == FFTC_OK) st = alloc_tables(p, segs, entries);
+    if (st == FFTC_OK && p->variant == FFTC_VARIANT_TWO_PASS && !t_plan_no_scratch) {
+        p->scratch_bytes = (size_t)batch * (size_t)n * csize_of(dtype);
+        hipError_t e = hipMalloc(&p->scratch, p->scratch_bytes);
+        if (e != hipSuccess) st = fail_hip(e, "hipMalloc(two-pass scratch)");
     }
     if (st != FFTC_OK) {
         std::string keep = t_last_error;
@@ -264,6 +280,10 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
     }
     *out = p;
     return FFTC_OK;
+}
+
+fftc_status check_static_args(int64_t n, int64_t batch, int direction, int dtype) {
+    return check_plan_args(n, batch, direction, dtype, nullptr, 0);
 }
 
 }  // namespace fftc

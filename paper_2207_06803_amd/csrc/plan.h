@@ -63,6 +63,15 @@ fftc_status launch_two_pass(const fftc_plan_s* p, const void* in, void* out, int
 fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count);
 fftc_status launch_mixed(fftc_plan_s* p, const void* in, void* out, hipStream_t s);
 void destroy_mixed(MixedState* m);
+// Radix lists, variant, launch shape and twiddle segments of a Stockham,
+// two-pass or split plan (fields of *p other than n, batch, direction and
+// dtype); touches no device memory.
+fftc_status shape_plan(fftc_plan_s* p, const int* radices, int count, std::vector<TwSegment>* segs,
+                       int64_t* entries);
+// fftc_plan's argument checks for a plan without an explicit radix list.
+fftc_status check_static_args(int64_t n, int64_t batch, int direction, int dtype);
+// Let the dynamic-LDS kernels use up to the per-workgroup maximum (once).
+fftc_status enable_large_lds();
 // Fill a runtime descriptor for a radix list (twoff relative to twbase).
 void fill_gen_desc(int64_t n, const std::vector<int>& rs, int tpt, int t, int64_t twbase, GenDesc* d);
 

@@ -2,7 +2,7 @@
 //
 // Each segment describes entries value(idx) = w_L^{(m a b) mod L} with
 // a = idx / ns + a0 (a0 = 1 unless stated), b = idx mod ns and
-// w_L = exp(-2 pi i / L).  For a
+// w_L = exp(-2 pi i / L) (twiddle_dev.h computes one entry).  For a
 // Stockham stage of radix R after Ns (the twiddle diagonal of Eq. 2 at
 // length Ns R) this is the [r - 1][k] table of w_{Ns R}^{r k}; with ns = L
 // it is the plain table w_L^b, and with a multiplier m the coarse table
@@ -12,6 +12,7 @@
 // sincospi, so the quarter turns come out exact.  complex64 plans round
 // the fp64 value to nearest fp32.
 #include "internal.h"
+#include "twiddle_dev.h"
 
 namespace fftc {
 
@@ -23,18 +24,8 @@ template <typename C>
 __global__ void twiddle_kernel(C* table, const TwSegDev* __restrict__ segs) {
     const TwSegDev s = segs[blockIdx.y];
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < s.count;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t a = idx / s.ns + s.a0, b = idx % s.ns;
-        int64_t m = ((s.mul * a) % s.len) * b % s.len;
-        if (2 * m > s.len) m -= s.len;  // angle in (-pi, pi]
-        double sn, cs;
-        // w = exp(-2 pi i m / L) = cos(2 pi m/L) - i sin(2 pi m/L)
-        sincospi(2.0 * (double)m / (double)s.len, &sn, &cs);
-        C v;
-        v.x = cs;
-        v.y = -sn;
-        table[s.off + idx] = v;
-    }
+         idx += (int64_t)gridDim.x * blockDim.x)
+        table[s.off + idx] = twiddle_entry<C>(idx, s.ns, s.len, s.mul, s.a0);
 }
 
 fftc_status make_twiddles(void* table, int dtype, const std::vector<TwSegment>& segs,

@@ -109,6 +109,8 @@ _SIGNATURES = {
     "fftc_autotune_orders": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(_int), ctypes.POINTER(_int),
                                     ctypes.POINTER(ctypes.c_double), _int, ctypes.POINTER(_int),
                                     ctypes.POINTER(_int)]),
+    "fftc_execute_static": (_int, [_i64, _i64, _int, _int, _vp, _vp, _vp]),
+    "fftc_static_scratch_bytes": (ctypes.c_size_t, []),
     "fftc_status_string": (ctypes.c_char_p, [_int]),
     "fftc_last_error": (ctypes.c_char_p, []),
 }
@@ -496,6 +498,23 @@ def copy(x, y, nbytes: int, stream=None) -> None:
     check_extent(x, int(nbytes), "copy source")
     check_extent(y, int(nbytes), "copy destination")
     check(lib.fftc_copy(ptr(x), ptr(y), int(nbytes), stream_handle(stream)), "fftc_copy")
+
+
+def execute_static(n: int, batch: int, x, y, direction: int = FORWARD, dtype="c64", stream=None) -> None:
+    """Plan and run `batch` transforms of length n in one call that allocates
+    no device memory (tables and any in-place intermediate in the library's
+    static device array); calls overlapping in time on one GPU race."""
+    code = dtype_code(dtype)
+    nbytes = int(n) * int(batch) * (16 if code == C128 else 8)
+    dev = _current_device()
+    check_extent(x, nbytes, "input", dev)
+    check_extent(y, nbytes, "output", dev)
+    check(lib.fftc_execute_static(int(n), int(batch), int(direction), code, ptr(x), ptr(y), stream_handle(stream)),
+          "fftc_execute_static")
+
+
+def static_scratch_bytes() -> int:
+    return int(lib.fftc_static_scratch_bytes())
 
 
 def max_single_n(dtype="c64") -> int:
