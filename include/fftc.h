@@ -311,25 +311,34 @@ fftc_status fftc_copy(const void *in, void *out, size_t bytes, void *stream);
  * back in that order (transform i starts at element n[0] + ... + n[i-1]) in
  * both in and out.  Every length must satisfy 1 <= n[i] <= 4096 with prime
  * factors <= 7.  The uneven batch runs as one persistent launch: equal lengths
- * form classes with their own radix list (tuning database or heuristic), work
- * items are ordered longest first and pulled by the resident workgroups from
- * an atomic counter, which the last workgroup to finish clears again.  The
+ * form classes with their own radix list (tuning database or heuristic), and
+ * the plan assigns the work items, longest first, each to the resident
+ * workgroup with the least work so far; a workgroup fetches its next item's
+ * descriptor while it runs the current one.  The
  * launch is recorded in a hipGraph at plan time; fftc_execute replays it on
  * the caller's stream (updating the graph's pointer arguments when in/out
- * change).  Executions of one mixed plan must not overlap (they share the
- * work counter).
+ * change).  Executions of one mixed plan on different streams must not
+ * overlap: they share the plan's one instantiated graph, whose pointer
+ * arguments a call with other in/out updates.
  */
 fftc_status fftc_plan_mixed(const int64_t *n, int64_t count, int direction, int dtype,
                             fftc_plan_t *plan_out);
 
 /*
- * Autotuner.  Times every candidate Stockham radix list for single-kernel
- * length n (batch transforms, forward, on an internal stream with scratch
- * buffers it allocates and frees), keeps the fastest -- ties within 1% go to
- * fewer stages, then to the larger leading radix -- and records it in the
- * process's tuning database, which later plans for (n, dtype) use.  Returns
- * the chosen list in radices[0..*count) and its mean time per launch in
- * microseconds.  `reps` launches per timing (>= 1).  Synchronous.
+ * Autotuner (the planner the paper names as missing, Section VI; different
+ * factorisations suit different hardware, Section I).  Times every
+ * candidate Stockham radix list for single-kernel length n, forward, on an
+ * internal stream, at the HBM-bound shape: max(batch, 2^24 / n) transforms
+ * per launch, launches rotating over four input/output pairs that it
+ * allocates and frees (1 GiB for complex64 at 2^24 elements), each launch
+ * timed by its own events.  A candidate's time is the median of `reps`
+ * launches (1 <= reps <= 100000; 20 or more gives stable picks); two
+ * candidates tie unless their medians differ by more than twice the larger
+ * relative interquartile range of their launches (at least 1%), and ties go
+ * to fewer stages, then to the larger leading radix.  The winner is recorded
+ * in the process's tuning database, which later plans for (n, dtype) use.
+ * Returns the chosen list in radices[0..*count) and its median time per
+ * launch in microseconds.  Synchronous.
  */
 fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int *radices,
                           int max_count, int *count, double *best_us);
@@ -362,12 +371,12 @@ fftc_status fftc_order_entry(int dtype, int i, int64_t *n, int *order, int *radi
 
 /*
  * Order autotuner: times the Stockham plan (its tuned or preferred list) and
- * every compiled (order, radix) for n, like fftc_autotune (best of three
- * trials of `reps` launches, forward, internal buffers).  Writes up to `max`
- * results (orders[i], radices[i] -- 0 for Stockham -- and us[i]), the count,
- * and the index of the fastest; a non-Stockham order wins only by more than
- * 1%.  The winner is recorded in the tuning database, and fftc_plan then
- * uses that order for (n, dtype).
+ * every compiled (order, radix) for n, like fftc_autotune (median of `reps`
+ * launches at the HBM-bound shape, rotating internal buffers).  Writes up to
+ * `max` results (orders[i], radices[i] -- 0 for Stockham -- and us[i]), the
+ * count, and the index of the fastest; a non-Stockham order wins only beyond
+ * the tie window.  The winner is recorded in the tuning database, and
+ * fftc_plan then uses that order for (n, dtype).
  */
 fftc_status fftc_autotune_orders(int64_t n, int64_t batch, int dtype, int reps, int *orders, int *radices,
                                  double *us, int max, int *count, int *best);

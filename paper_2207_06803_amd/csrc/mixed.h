@@ -6,6 +6,10 @@
 namespace fftc {
 
 constexpr int kMixedThreads = 256;             // threads per persistent workgroup
+// Resident workgroups per CU the kernel is compiled for (its register budget:
+// 512 / (groups x waves per group) VGPRs per lane): three for complex64,
+// two for complex128, whose bodies hold twice the registers.
+template <typename Real> constexpr int mixed_groups_per_cu() { return sizeof(Real) == 4 ? 3 : 2; }
 constexpr int kMixedMaxLen = 4096;             // longest transform in a mixed plan
 constexpr int kMixedLdsElems = lds_len(4096);  // LDS elements per workgroup
 
@@ -18,10 +22,14 @@ struct MixedClass {
 };
 
 struct MixedItem {
-    int cls;    // class index
-    int first;  // first entry in the grouped transform-offset list
-    int count;  // transforms in this item (<= desc.t)
-    int pad;
+    int cls;     // class index
+    int first;   // first entry in the grouped transform-offset list
+    int count;   // transforms in this item (<= desc.t <= kMixedThreads)
+    int body;    // the class's compiled list (spec_list.inc id), -1: runtime radices
+    int twbase;  // the class's first twiddle in the shared table
+    int n;       // transform length
+    int ldsn;    // LDS elements per transform (compiled bodies leave results there)
+    uint32_t magic;  // ceil(2^32 / n): floor(l / n) = umulhi(l, magic) for l < 2^32 / n
 };
 
 // Persistent kernels (mixed_c64.hip / mixed_c128.hip).
@@ -37,11 +45,11 @@ struct MixedState {
     int64_t count = 0, total = 0;
     int nitems = 0, groups = 0;
     size_t lds_bytes = 0;
-    void* dev = nullptr;  // one allocation: counter, classes, items, offsets, twiddles
+    void* dev = nullptr;  // one allocation: classes, items, workgroup ranges, offsets, twiddles
     size_t dev_bytes = 0;
-    unsigned int* counter = nullptr;  // [0] next item, [1] workgroups finished
     MixedClass* d_classes = nullptr;
     MixedItem* d_items = nullptr;
+    int* d_wg_start = nullptr;  // workgroup g runs items [wg_start[g], wg_start[g + 1])
     int64_t* d_offsets = nullptr;
     void* d_tw = nullptr;
     hipGraph_t graph = nullptr;
@@ -49,7 +57,7 @@ struct MixedState {
     hipGraphNode_t kernel_node = nullptr;
     const void* fn = nullptr;
     MixedArgs args{};
-    void* kargs[8] = {};
+    void* kargs[7] = {};
     std::vector<int64_t> class_len;
     std::vector<std::vector<int>> class_radices;
 

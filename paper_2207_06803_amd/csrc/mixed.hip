@@ -5,16 +5,16 @@
 // its own Stockham radix list (from the tuning database or the planner) and
 // twiddle segment in one shared table.  Work items hold up to T_c transforms
 // of one class -- as many as one 256-thread workgroup can hold in registers
-// and LDS -- and are ordered by decreasing cost (longest processing time
-// first).  A grid sized to fill the GPU once pulls items from an atomic
-// counter until the list is exhausted; every workgroup leaves the loop after
-// reading an index past the end, and the last one to leave clears the
-// counters for the next launch.  The launch is recorded in a hipGraph at plan
-// time and replayed per execution.
+// and LDS.  A grid sized to fill the GPU once runs them: the plan assigns the
+// items, longest first, each to the workgroup with the least work so far
+// (longest-processing-time scheduling, work = bytes moved plus a fixed cost
+// per item), and lays each workgroup's items out contiguously.  The launch
+// is recorded in a hipGraph at plan time and replayed per execution.
 #include <algorithm>
 #include <cmath>
 #include <map>
 #include <numeric>
+#include <queue>
 
 #include "plan.h"
 
@@ -99,55 +99,36 @@ fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count) {
     std::vector<int64_t> order;  // transform ids grouped by class
     std::vector<MixedItem> items;
     std::vector<double> cost;
+    // a fixed cost per item (descriptor and first-load latency) in bytes
+    const double kItemBytes = 16384.0;
     for (int c = 0; c < ncls; ++c) {
         const int t = classes[c].desc.t;
-        const double per = (double)lens[c] * std::log2((double)lens[c]);
+        if (t > kMixedThreads) return fail(FFTC_ERR_INTERNAL, "mixed item larger than a workgroup");
         for (size_t s = 0; s < members[c].size(); s += t) {
             MixedItem it{};
             it.cls = c;
             it.first = (int)order.size();
             it.count = (int)std::min<size_t>(t, members[c].size() - s);
+            it.body = classes[c].body;
+            it.twbase = classes[c].twbase;
+            it.n = (int)lens[c];
+            it.ldsn = classes[c].ldsn;
+            it.magic = lens[c] > 1 ? (uint32_t)(((uint64_t(1) << 32) + lens[c] - 1) / lens[c]) : 0;
+            if ((int64_t)t * lens[c] >= (int64_t(1) << 32) / std::max<int64_t>(lens[c], 1))
+                return fail(FFTC_ERR_INTERNAL, "mixed item too long for its index division");
             for (int q = 0; q < it.count; ++q) order.push_back(members[c][s + q]);
             items.push_back(it);
-            cost.push_back(per * it.count);
+            cost.push_back(2.0 * (double)cs * (double)lens[c] * it.count + kItemBytes);
         }
     }
-    // longest processing time first
-    std::vector<size_t> idx(items.size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<MixedItem> sorted(items.size());
-    for (size_t i = 0; i < idx.size(); ++i) sorted[i] = items[idx[i]];
+    if (order.size() > (size_t)0x7fffffff) return fail(FFTC_ERR_INVALID_ARG, "too many transforms");
     std::vector<int64_t> toffs(order.size());
     for (size_t i = 0; i < order.size(); ++i) toffs[i] = offsets[order[i]];
 
     m->count = count;
     m->total = total;
-    m->nitems = (int)sorted.size();
+    m->nitems = (int)items.size();
     m->lds_bytes = std::max<size_t>(lds_need, 16);
-
-    // device block: counter | classes | items | offsets | twiddles
-    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t o_cnt = 0;
-    const size_t o_cls = align(o_cnt + 2 * sizeof(unsigned int));
-    const size_t o_items = align(o_cls + sizeof(MixedClass) * ncls);
-    const size_t o_offs = align(o_items + sizeof(MixedItem) * sorted.size());
-    const size_t o_tw = align(o_offs + sizeof(int64_t) * toffs.size());
-    const size_t bytes = o_tw + (size_t)std::max<int64_t>(twoff, 1) * cs;
-    FFTC_HIP_TRY(hipMalloc(&m->dev, bytes));
-    m->dev_bytes = bytes;
-    char* base = static_cast<char*>(m->dev);
-    m->counter = reinterpret_cast<unsigned int*>(base + o_cnt);
-    m->d_classes = reinterpret_cast<MixedClass*>(base + o_cls);
-    m->d_items = reinterpret_cast<MixedItem*>(base + o_items);
-    m->d_offsets = reinterpret_cast<int64_t*>(base + o_offs);
-    m->d_tw = base + o_tw;
-    FFTC_HIP_TRY(hipMemcpy(m->d_classes, classes.data(), sizeof(MixedClass) * ncls, hipMemcpyHostToDevice));
-    FFTC_HIP_TRY(hipMemcpy(m->d_items, sorted.data(), sizeof(MixedItem) * sorted.size(), hipMemcpyHostToDevice));
-    FFTC_HIP_TRY(hipMemcpy(m->d_offsets, toffs.data(), sizeof(int64_t) * toffs.size(), hipMemcpyHostToDevice));
-    FFTC_HIP_TRY(hipMemset(m->counter, 0, 2 * sizeof(unsigned int)));
-    fftc_status st = make_twiddles(m->d_tw, dtype, segs, nullptr);
-    if (st != FFTC_OK) return st;
 
     // persistent grid: every resident workgroup slot once
     const void* fn = mixed_fn(dtype, p->direction);
@@ -156,9 +137,57 @@ fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count) {
     FFTC_HIP_TRY(hipGetDevice(&dev));
     FFTC_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     FFTC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kMixedThreads, m->lds_bytes));
-    m->groups = std::max(1, std::min(per_cu * cus, m->nitems));
+    const int groups = std::max(1, std::min(per_cu * cus, m->nitems));
+    m->groups = groups;
 
-    // graph: the persistent kernel (it leaves the counters cleared)
+    // longest first, each to the least loaded workgroup; a workgroup's items
+    // are contiguous, in the order it received them
+    std::vector<size_t> idx(items.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    using Load = std::pair<double, int>;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int g = 0; g < groups; ++g) heap.push({0.0, g});
+    std::vector<std::vector<int>> per_wg(groups);
+    for (size_t i : idx) {
+        Load l = heap.top();
+        heap.pop();
+        per_wg[l.second].push_back((int)i);
+        heap.push({l.first + cost[i], l.second});
+    }
+    std::vector<MixedItem> sorted;
+    sorted.reserve(items.size());
+    std::vector<int> wg_start(groups + 1, 0);
+    for (int g = 0; g < groups; ++g) {
+        wg_start[g] = (int)sorted.size();
+        for (int i : per_wg[g]) sorted.push_back(items[i]);
+    }
+    wg_start[groups] = (int)sorted.size();
+
+    // device block: classes | items | workgroup ranges | offsets | twiddles
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_cls = 0;
+    const size_t o_items = align(o_cls + sizeof(MixedClass) * ncls);
+    const size_t o_wg = align(o_items + sizeof(MixedItem) * sorted.size());
+    const size_t o_offs = align(o_wg + sizeof(int) * wg_start.size());
+    const size_t o_tw = align(o_offs + sizeof(int64_t) * toffs.size());
+    const size_t bytes = o_tw + (size_t)std::max<int64_t>(twoff, 1) * cs;
+    FFTC_HIP_TRY(hipMalloc(&m->dev, bytes));
+    m->dev_bytes = bytes;
+    char* base = static_cast<char*>(m->dev);
+    m->d_classes = reinterpret_cast<MixedClass*>(base + o_cls);
+    m->d_items = reinterpret_cast<MixedItem*>(base + o_items);
+    m->d_wg_start = reinterpret_cast<int*>(base + o_wg);
+    m->d_offsets = reinterpret_cast<int64_t*>(base + o_offs);
+    m->d_tw = base + o_tw;
+    FFTC_HIP_TRY(hipMemcpy(m->d_classes, classes.data(), sizeof(MixedClass) * ncls, hipMemcpyHostToDevice));
+    FFTC_HIP_TRY(hipMemcpy(m->d_items, sorted.data(), sizeof(MixedItem) * sorted.size(), hipMemcpyHostToDevice));
+    FFTC_HIP_TRY(hipMemcpy(m->d_wg_start, wg_start.data(), sizeof(int) * wg_start.size(), hipMemcpyHostToDevice));
+    FFTC_HIP_TRY(hipMemcpy(m->d_offsets, toffs.data(), sizeof(int64_t) * toffs.size(), hipMemcpyHostToDevice));
+    fftc_status st = make_twiddles(m->d_tw, dtype, segs, nullptr);
+    if (st != FFTC_OK) return st;
+
+    // graph: the persistent kernel
     FFTC_HIP_TRY(hipGraphCreate(&m->graph, 0));
     {
         m->args.in = nullptr;
@@ -177,9 +206,8 @@ hipKernelNodeParams MixedState::kernel_params(const void* fn_) {
     kargs[2] = &d_tw;
     kargs[3] = &d_classes;
     kargs[4] = &d_items;
-    kargs[5] = &d_offsets;
-    kargs[6] = &nitems;
-    kargs[7] = &counter;
+    kargs[5] = &d_wg_start;
+    kargs[6] = &d_offsets;
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn_);
     kp.gridDim = dim3((unsigned)groups);

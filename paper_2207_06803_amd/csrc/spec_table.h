@@ -18,9 +18,10 @@ struct SpecInst {
     using KF = SpecCfg<Real, N, TPT, T, false>;
     using KI = SpecCfg<Real, N, TPT, T, true>;
     template <bool INV> using K = typename std::conditional<INV, KI, KF>::type;
-    // bodies of the persistent mixed kernel: 256-thread workgroups
+    // bodies of the persistent mixed kernel: 256-thread workgroups, results
+    // left in LDS for the kernel to store
     static constexpr int TM = pick_t_for(kWorkgroupTarget, TPT, N, (int)sizeof(cplx<Real>), NR > 1);
-    template <bool INV> using KM = SpecCfg<Real, N, TPT, TM, INV>;
+    template <bool INV> using KM = SpecCfg<Real, N, TPT, TM, INV, true>;
     static SpecEntry entry(int dtype, int id) {
         SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
                     reinterpret_cast<const void*>(&stockham_spec<KF, Rs...>),
@@ -54,18 +55,25 @@ struct SpecInst {
 };
 
 // One work item of a compiled list inside the persistent mixed-length kernel:
-// `count` transforms at offsets offs[0..count) (not inlined, so each body
-// keeps its own registers).
+// `count` transforms at offsets offs[0..count), results left in LDS (not
+// inlined, so each body keeps its own registers; a function waits for its
+// stores before it returns, so the kernel stores instead).  Internal linkage:
+// every call site is in the one kernel, so the compiler sees that `lds` and
+// `offs` point into LDS and emits LDS instructions for them rather than
+// generic (flat) accesses; the global data goes through pointers typed as
+// global memory for the same reason.
 struct ListOff {
     const int64_t* offs;
     __device__ __forceinline__ int64_t operator()(int q) const { return offs[q]; }
 };
 
 template <class K, int NTH, int... Rs>
-__device__ __noinline__ void spec_body(const typename K::C* in, typename K::C* out, const int64_t* offs,
-                                       int count, typename K::C* lds, const typename K::C* __restrict__ tw,
-                                       int tid) {
-    spec_group<K, NTH, ListOff, Rs...>(in, out, ListOff{offs}, count, lds, tw, tid);
+static __device__ __noinline__ void spec_body(const typename K::C* in, const int64_t* offs, int count,
+                                              typename K::C* lds, const typename K::C* __restrict__ tw, int tid) {
+    using C = typename K::C;
+    static_assert(K::OUT_LDS, "mixed bodies leave their results in LDS");
+    spec_group<K, NTH, ListOff, Rs...>(GIn<C>{(const FFTC_GLOBAL C*)in}, GOut<C>{nullptr}, ListOff{offs}, count,
+                                       lds, tw, tid);
 }
 
 }  // namespace fftc

@@ -38,6 +38,39 @@ template <bool INV, typename C> __device__ __forceinline__ void st_out(C* p, C v
     __builtin_nontemporal_store(t, reinterpret_cast<V*>(p));
 }
 
+// Contiguous data through pointers typed as global memory: for code outside a
+// kernel (the mixed kernel's bodies are functions), where a plain pointer
+// argument would be accessed with generic (flat) instructions.
+#define FFTC_GLOBAL __attribute__((address_space(1)))
+template <typename C> struct GIn {
+    const FFTC_GLOBAL C* p;
+};
+template <typename C> struct GOut {
+    FFTC_GLOBAL C* p;
+};
+template <typename C> __device__ __forceinline__ GIn<C> gshift(GIn<C> a, int64_t off) {
+    a.p += off;
+    return a;
+}
+template <typename C> __device__ __forceinline__ GOut<C> gshift(GOut<C> a, int64_t off) {
+    a.p += off;
+    return a;
+}
+template <bool INV, typename C> __device__ __forceinline__ C gld(const GIn<C>& a, int e) {
+    using V = typename vec_of<C>::type;
+    const V t = __builtin_nontemporal_load(reinterpret_cast<const FFTC_GLOBAL V*>(a.p + e));
+    C v = mk(t.x, t.y);
+    return INV ? cconj(v) : v;
+}
+template <bool INV, typename C> __device__ __forceinline__ void gst(const GOut<C>& a, int e, C v) {
+    using V = typename vec_of<C>::type;
+    if (INV) v = cconj(v);
+    V t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<FFTC_GLOBAL V*>(a.p + e));
+}
+
 // Any other layout (planar re / im arrays, element strides, gaps between
 // transforms): element e of transform q at re[q ts + e es] and
 // im[q ts + e es] (interleaved complex: im = re + 1 and es, ts counted in
@@ -127,17 +160,25 @@ template <bool INV, typename Real> __device__ __forceinline__ void gst(const GAc
 // r = 1, 2, 3 and r = 4, 8, 12 are read and the rest formed as one product
 // w^{r k} = w^{(r mod 4) k} w^{4 (r div 4) k}: 6 loads instead of 15 for
 // radix 16 (one extra rounding in the formed factors).
-template <int R, typename C>
-__device__ __forceinline__ void apply_twiddles_ns(C* v, const C* __restrict__ tq, int ns) {
+// Entry k of a twiddle table, through a plain or a global-typed pointer.
+template <typename C> __device__ __forceinline__ C ldtw(const C* p, int k) { return p[k]; }
+template <typename C> __device__ __forceinline__ C ldtw(const FFTC_GLOBAL C* p, int k) {
+    using V = typename vec_of<C>::type;
+    const V t = *reinterpret_cast<const FFTC_GLOBAL V*>(p + k);
+    return mk(t.x, t.y);
+}
+
+template <int R, typename C, typename P>
+__device__ __forceinline__ void apply_twiddles_ns(C* v, P tq, int ns) {
     if constexpr (R == 16 || R == 8) {
         C a[4], b[4];
-        a[1] = tq[0 * ns];
-        a[2] = tq[1 * ns];
-        a[3] = tq[2 * ns];
-        b[1] = tq[3 * ns];
+        a[1] = ldtw(tq, 0 * ns);
+        a[2] = ldtw(tq, 1 * ns);
+        a[3] = ldtw(tq, 2 * ns);
+        b[1] = ldtw(tq, 3 * ns);
         if constexpr (R == 16) {
-            b[2] = tq[7 * ns];
-            b[3] = tq[11 * ns];
+            b[2] = ldtw(tq, 7 * ns);
+            b[3] = ldtw(tq, 11 * ns);
         }
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -147,12 +188,12 @@ __device__ __forceinline__ void apply_twiddles_ns(C* v, const C* __restrict__ tq
         }
     } else {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tq[(r - 1) * ns]);
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], ldtw(tq, (r - 1) * ns));
     }
 }
 
-template <int R, int NS, typename C>
-__device__ __forceinline__ void apply_twiddles(C* v, const C* __restrict__ tq) {
+template <int R, int NS, typename C, typename P>
+__device__ __forceinline__ void apply_twiddles(C* v, P tq) {
     apply_twiddles_ns<R>(v, tq, NS);
 }
 
@@ -167,13 +208,17 @@ __device__ __forceinline__ void apply_twiddles(C* v, const C* __restrict__ tq) {
 // loaded cooperatively with consecutive lanes on consecutive elements into
 // LDS, transformed LDS to LDS, and stored back the same way.
 // ---------------------------------------------------------------------------
-template <typename Real, int N_, int TPT_, int T_, bool INV_>
+// OUT_LDS: the group's results stay in LDS (transform q at q LDSN, element e
+// at lds_pad(e), natural order, conjugated for the inverse) for the caller to
+// store.
+template <typename Real, int N_, int TPT_, int T_, bool INV_, bool OUT_LDS_ = false>
 struct SpecCfg {
     using RealT = Real;
     using C = cplx<Real>;
     static constexpr int N = N_, TPT = TPT_, T = T_;
     static constexpr bool INV = INV_;
     static constexpr bool STAGED = TPT_ < 16;
+    static constexpr bool OUT_LDS = OUT_LDS_;
 };
 
 template <class K, int R, int NS, int TWOFF, bool SRC_G, bool DST_G, class GI, class GO>
@@ -200,7 +245,9 @@ __device__ __forceinline__ void spec_stage(GI gin, GO gout, typename K::C* lds,
                     v[i][r] = lds[lds_pad(j + r * NR)];
                 }
             }
-            if constexpr (NS > 1) apply_twiddles<R, NS>(v[i], tw + TWOFF + j % NS);
+            // the tables are global memory (typed so, also inside functions)
+            if constexpr (NS > 1)
+                apply_twiddles<R, NS>(v[i], (const FFTC_GLOBAL C*)tw + TWOFF + j % NS);
             Codelet<R, C>::run(v[i]);
         }
     }
@@ -236,7 +283,7 @@ __device__ __forceinline__ void spec_stages(GI gin, GO gout, typename K::C* lds,
 }
 
 template <class K, int NR> struct SpecLds {
-    static constexpr int LDSN = (NR > 1 || K::STAGED) ? lds_len(K::N) : 1;
+    static constexpr int LDSN = (NR > 1 || K::STAGED || K::OUT_LDS) ? lds_len(K::N) : 1;
 };
 
 // The transforms of one group: transform q < count starts at element toff(q)
@@ -270,16 +317,18 @@ __device__ __forceinline__ void spec_group(GI in, GO out, OffF toff, int count, 
         __syncthreads();
         spec_stages<K, 1, 0, true, false, false, Rs...>((const C*)nullptr, (C*)nullptr, mylds, tw, t, valid,
                                                          member);
+        if constexpr (!K::OUT_LDS) {
 #pragma unroll
-        for (int i = 0; i < ITER; ++i) {
-            const int l = tid + i * NTH;
-            const int q = l / N;
-            if (l < TOT && q < count) gst<K::INV>(gshift(out, toff(q)), l % N, lds[q * LDSN + lds_pad(l % N)]);
+            for (int i = 0; i < ITER; ++i) {
+                const int l = tid + i * NTH;
+                const int q = l / N;
+                if (l < TOT && q < count) gst<K::INV>(gshift(out, toff(q)), l % N, lds[q * LDSN + lds_pad(l % N)]);
+            }
         }
     } else {
         const int64_t off = toff(valid ? tr : 0);
-        spec_stages<K, 1, 0, true, true, true, Rs...>(gshift(in, off), gshift(out, off), mylds, tw, t, valid,
-                                                       member);
+        spec_stages<K, 1, 0, true, true, !K::OUT_LDS, Rs...>(gshift(in, off), gshift(out, off), mylds, tw, t,
+                                                              valid, member);
     }
 }
 

@@ -2,6 +2,8 @@
 // fastest in the tuning database (the planner the paper lacks, Section VI).
 #include <math.h>
 
+#include <algorithm>
+
 #include <string>
 
 #include "plan.h"
@@ -10,48 +12,83 @@ namespace fftc {
 
 namespace {
 
+// Candidates are timed at the HBM-bound shape: at least 2^24 elements per
+// launch, launches rotating over four input/output pairs (1 GiB in all for
+// complex64, past the 256 MB last-level cache), each launch timed by its own
+// event pair.
+constexpr int kTunePairs = 4;
+constexpr int64_t kTuneMinElems = int64_t(1) << 24;
+
 struct DeviceBuffers {
-    void* in = nullptr;
-    void* out = nullptr;
+    void* in[kTunePairs] = {};
+    void* out[kTunePairs] = {};
     hipStream_t s = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<hipEvent_t> ev;
     ~DeviceBuffers() {
-        if (e0) hipEventDestroy(e0);
-        if (e1) hipEventDestroy(e1);
+        for (hipEvent_t e : ev)
+            if (e) hipEventDestroy(e);
         if (s) hipStreamDestroy(s);
-        if (in) hipFree(in);
-        if (out) hipFree(out);
+        for (int i = 0; i < kTunePairs; ++i) {
+            if (in[i]) hipFree(in[i]);
+            if (out[i]) hipFree(out[i]);
+        }
     }
 };
 
-// Mean microseconds per launch: best of three trials of `reps` launches.
-fftc_status time_plan(fftc_plan_t p, DeviceBuffers& b, int reps, double* us) {
-    fftc_status st;
-    for (int i = 0; i < 2; ++i)
-        if ((st = fftc_execute(p, b.in, b.out, b.s)) != FFTC_OK) return st;
-    double best = 1e30;
-    for (int trial = 0; trial < 3; ++trial) {
-        FFTC_HIP_TRY(hipEventRecord(b.e0, b.s));
-        for (int i = 0; i < reps; ++i)
-            if ((st = fftc_execute(p, b.in, b.out, b.s)) != FFTC_OK) return st;
-        FFTC_HIP_TRY(hipEventRecord(b.e1, b.s));
-        FFTC_HIP_TRY(hipEventSynchronize(b.e1));
-        float ms = 0.f;
-        FFTC_HIP_TRY(hipEventElapsedTime(&ms, b.e0, b.e1));
-        best = std::min(best, 1000.0 * ms / reps);
+int64_t tune_batch(int64_t n, int64_t batch) { return std::max(batch, (kTuneMinElems + n - 1) / n); }
+
+fftc_status alloc_buffers(DeviceBuffers& b, size_t bytes, int reps) {
+    FFTC_HIP_TRY(hipStreamCreate(&b.s));
+    for (int i = 0; i < kTunePairs; ++i) {
+        FFTC_HIP_TRY(hipMalloc(&b.in[i], bytes));
+        FFTC_HIP_TRY(hipMalloc(&b.out[i], bytes));
+        FFTC_HIP_TRY(hipMemsetAsync(b.in[i], 0x3c, bytes, b.s));  // small finite values
     }
-    *us = best;
+    b.ev.assign(reps + 1, nullptr);
+    for (auto& e : b.ev) FFTC_HIP_TRY(hipEventCreate(&e));
     return FFTC_OK;
 }
 
-// a better than b: faster by more than 1%, else fewer stages, else larger
-// leading radix
-bool better(double ta, const std::vector<int>& a, double tb, const std::vector<int>& b) {
-    if (ta < 0.99 * tb) return true;
-    if (tb < 0.99 * ta) return false;
+struct Timing {
+    double med = 0, spread = 0;  // median microseconds per launch; interquartile range / median
+};
+
+fftc_status time_plan(fftc_plan_t p, DeviceBuffers& b, int reps, Timing* t) {
+    fftc_status st;
+    for (int i = 0; i < 2 * kTunePairs; ++i)
+        if ((st = fftc_execute(p, b.in[i % kTunePairs], b.out[i % kTunePairs], b.s)) != FFTC_OK) return st;
+    FFTC_HIP_TRY(hipEventRecord(b.ev[0], b.s));
+    for (int i = 0; i < reps; ++i) {
+        if ((st = fftc_execute(p, b.in[i % kTunePairs], b.out[i % kTunePairs], b.s)) != FFTC_OK) return st;
+        FFTC_HIP_TRY(hipEventRecord(b.ev[i + 1], b.s));
+    }
+    FFTC_HIP_TRY(hipEventSynchronize(b.ev[reps]));
+    std::vector<double> us(reps);
+    for (int i = 0; i < reps; ++i) {
+        float ms = 0.f;
+        FFTC_HIP_TRY(hipEventElapsedTime(&ms, b.ev[i], b.ev[i + 1]));
+        us[i] = 1000.0 * ms;
+    }
+    std::sort(us.begin(), us.end());
+    auto q = [&](double f) { return us[(size_t)std::min<double>(reps - 1, std::floor(f * (reps - 1) + 0.5))]; };
+    t->med = q(0.5);
+    t->spread = t->med > 0 ? (q(0.75) - q(0.25)) / t->med : 0;
+    return FFTC_OK;
+}
+
+// Two medians differ when they are further apart than the launches' own
+// spread (twice the larger relative interquartile range, at least 1%).
+double tie_window(const Timing& a, const Timing& b) { return std::max(0.01, 2.0 * std::max(a.spread, b.spread)); }
+
+// a better than b: faster beyond the tie window, else fewer stages, else
+// larger leading radix
+bool better(const Timing& ta, const std::vector<int>& a, const Timing& tb, const std::vector<int>& b) {
+    const double w = tie_window(ta, tb);
+    if (ta.med < (1 - w) * tb.med) return true;
+    if (tb.med < (1 - w) * ta.med) return false;
     if (a.size() != b.size()) return a.size() < b.size();
     if (!a.empty() && !b.empty() && a[0] != b[0]) return a[0] > b[0];
-    return ta < tb;
+    return ta.med < tb.med;
 }
 
 }  // namespace
@@ -67,38 +104,35 @@ fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int* ra
     if (!count || (max_count > 0 && !radices)) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
     if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
     if (batch < 1 || reps < 1) return fail(FFTC_ERR_INVALID_ARG, "batch and reps must be >= 1");
+    if (reps > 100000) return fail(FFTC_ERR_INVALID_ARG, "reps must be <= 100000");
     if (n < 2 || n > max_single_n(dtype) || !is_7smooth(n))
         return fail(FFTC_ERR_UNSUPPORTED_SIZE, "autotune takes single-kernel lengths 2.." +
                                                    std::to_string(max_single_n(dtype)));
     try {
         const size_t cs = dtype == FFTC_C128 ? 16 : 8;
-        const size_t bytes = (size_t)batch * (size_t)n * cs;
+        const int64_t tb = tune_batch(n, batch);
         DeviceBuffers b;
-        FFTC_HIP_TRY(hipMalloc(&b.in, bytes));
-        FFTC_HIP_TRY(hipMalloc(&b.out, bytes));
-        FFTC_HIP_TRY(hipStreamCreate(&b.s));
-        FFTC_HIP_TRY(hipEventCreate(&b.e0));
-        FFTC_HIP_TRY(hipEventCreate(&b.e1));
-        FFTC_HIP_TRY(hipMemsetAsync(b.in, 0x3c, bytes, b.s));  // small finite values
+        fftc_status sa = alloc_buffers(b, (size_t)tb * (size_t)n * cs, reps);
+        if (sa != FFTC_OK) return sa;
         std::vector<int> best;
-        double best_t = 0;
+        Timing best_t;
         for (const auto& rs : radix_candidates(n, 12)) {
             fftc_plan_t p = nullptr;
-            fftc_status st = fftc_plan_radices(n, batch, FFTC_FORWARD, dtype, rs.data(), (int)rs.size(), &p);
+            fftc_status st = fftc_plan_radices(n, tb, FFTC_FORWARD, dtype, rs.data(), (int)rs.size(), &p);
             if (st != FFTC_OK) continue;  // list does not fit this device's limits
-            double us = 0;
-            st = time_plan(p, b, reps, &us);
+            Timing t;
+            st = time_plan(p, b, reps, &t);
             fftc_destroy_plan(p);
             if (st != FFTC_OK) return st;
-            if (best.empty() || better(us, rs, best_t, best)) {
+            if (best.empty() || better(t, rs, best_t, best)) {
                 best = rs;
-                best_t = us;
+                best_t = t;
             }
         }
         if (best.empty()) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no candidate radix list could be planned");
-        tune_record(n, dtype, best, best_t * 1e-3);
+        tune_record(n, dtype, best, best_t.med * 1e-3);
         *count = (int)best.size();
-        if (best_us) *best_us = best_t;
+        if (best_us) *best_us = best_t.med;
         if ((int)best.size() > max_count) return fail(FFTC_ERR_INVALID_ARG, "max_count too small");
         for (size_t i = 0; i < best.size(); ++i) radices[i] = best[i];
         return FFTC_OK;
@@ -113,19 +147,16 @@ fftc_status fftc_autotune_orders(int64_t n, int64_t batch, int dtype, int reps, 
     if (!count || !best || (max > 0 && (!orders || !radices || !us))) return fail(FFTC_ERR_INVALID_ARG, "NULL argument");
     if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
     if (batch < 1 || reps < 1) return fail(FFTC_ERR_INVALID_ARG, "batch and reps must be >= 1");
+    if (reps > 100000) return fail(FFTC_ERR_INVALID_ARG, "reps must be <= 100000");
     if (n < 2 || n > max_single_n(dtype) || !is_7smooth(n))
         return fail(FFTC_ERR_UNSUPPORTED_SIZE, "autotune takes single-kernel lengths 2.." +
                                                    std::to_string(max_single_n(dtype)));
     try {
         const size_t cs = dtype == FFTC_C128 ? 16 : 8;
-        const size_t bytes = (size_t)batch * (size_t)n * cs;
+        const int64_t tb = std::min<int64_t>(tune_batch(n, batch), int64_t(1) << 31);
         DeviceBuffers b;
-        FFTC_HIP_TRY(hipMalloc(&b.in, bytes));
-        FFTC_HIP_TRY(hipMalloc(&b.out, bytes));
-        FFTC_HIP_TRY(hipStreamCreate(&b.s));
-        FFTC_HIP_TRY(hipEventCreate(&b.e0));
-        FFTC_HIP_TRY(hipEventCreate(&b.e1));
-        FFTC_HIP_TRY(hipMemsetAsync(b.in, 0x3c, bytes, b.s));  // small finite values
+        fftc_status sa = alloc_buffers(b, (size_t)tb * (size_t)n * cs, reps);
+        if (sa != FFTC_OK) return sa;
         // candidates: the Stockham plan, then every compiled order for n
         std::vector<std::pair<int, int>> cands{{FFTC_ORDER_STOCKHAM, 0}};
         int cnt = 0;
@@ -133,32 +164,33 @@ fftc_status fftc_autotune_orders(int64_t n, int64_t batch, int dtype, int reps, 
         for (int i = 0; i < cnt; ++i)
             if (tab[i].n == n) cands.push_back({tab[i].order, tab[i].radix});
         const std::vector<int> stock = choose_radices(n, dtype);
-        std::vector<double> times;
+        std::vector<Timing> times;
         for (const auto& c : cands) {
             fftc_plan_t p = nullptr;
             fftc_status st = c.first == FFTC_ORDER_STOCKHAM
-                                 ? fftc_plan_radices(n, batch, FFTC_FORWARD, dtype, stock.data(), (int)stock.size(), &p)
-                                 : fftc_plan_order(n, batch, FFTC_FORWARD, dtype, c.first, c.second, &p);
+                                 ? fftc_plan_radices(n, tb, FFTC_FORWARD, dtype, stock.data(), (int)stock.size(), &p)
+                                 : fftc_plan_order(n, tb, FFTC_FORWARD, dtype, c.first, c.second, &p);
             if (st != FFTC_OK) return st;
-            double t = 0;
+            Timing t;
             st = time_plan(p, b, reps, &t);
             fftc_destroy_plan(p);
             if (st != FFTC_OK) return st;
             times.push_back(t);
         }
-        size_t bi = 0;  // Stockham unless another order is faster by more than 1%
+        // Stockham unless another order is faster beyond the tie window
+        size_t bi = 0;
         for (size_t i = 1; i < cands.size(); ++i)
-            if (times[i] < 0.99 * times[bi] && (bi != 0 || times[i] < 0.99 * times[0])) bi = i;
+            if (times[i].med < (1 - tie_window(times[i], times[bi])) * times[bi].med) bi = i;
         if (bi == 0)
-            tune_record(n, dtype, stock, times[0] * 1e-3);
+            tune_record(n, dtype, stock, times[0].med * 1e-3);
         else
-            tune_record_order(n, dtype, cands[bi].first, cands[bi].second, times[bi] * 1e-3);
+            tune_record_order(n, dtype, cands[bi].first, cands[bi].second, times[bi].med * 1e-3);
         *count = (int)cands.size();
         *best = (int)bi;
         for (int i = 0; i < (int)cands.size() && i < max; ++i) {
             orders[i] = cands[i].first;
             radices[i] = cands[i].second;
-            us[i] = times[i];
+            us[i] = times[i].med;
         }
         return FFTC_OK;
     } catch (...) {
