@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
                     help="write profiles/hbm_traffic.json from FETCH_SIZE / WRITE_SIZE runs of the headline "
                          "and of --calibrate-copy, then exit")
+    ap.add_argument("--profile-set", default="",
+                    help="only launch the named hot-path kernels a few times each, for counter runs: comma-separated "
+                         "from mixed, split, two_pass, c64_16384, copy")
     ap.add_argument("--extras", default="",
                     help="comma-separated names of the extra workloads to run (default: all)")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -722,6 +725,60 @@ def cpu_baseline(seconds):
             "precision_study_oracle": precision}
 
 
+def profile_set(names, torch, fftc, synth):
+    """A few launches of each named hot-path kernel at its benchmark shape,
+    over rotating buffers, for rocprofv3 counter runs (no timing here)."""
+    names = [n for n in names.split(",") if n]
+    s = torch.cuda.current_stream()
+
+    def launches(tag, plans, xs, ys, count=5):
+        for i in range(count + 2):
+            k = i % len(xs)
+            plans[k % len(plans)].execute(xs[k], ys[k], s)
+        torch.cuda.synchronize()
+        log(f"profile-set: {tag} done")
+
+    if "mixed" in names:
+        lengths = synth.draw_mixed_sizes(synth.rng(2), 10000)
+        tot = int(lengths.sum())
+        x = torch.from_numpy(synth.uniform_complex(synth.rng(2, 1), (tot,), np.complex64)).to("cuda")
+        xs = [x] + [x.clone() for _ in range(NBUF - 1)]
+        ys = [torch.empty_like(x) for _ in range(NBUF)]
+        plans = [fftc.plan_mixed(lengths) for _ in range(NBUF)]
+        launches("mixed 10,000 transforms (default planner lists)", plans, xs, ys)
+        for p in plans:
+            p.close()
+        del x, xs, ys
+    if "split" in names:
+        for n in (1024, 4096, 16384):
+            b = 8192
+            x = torch.from_numpy(synth.gaussian_complex(synth.rng(4, n), (b * n,), np.complex64)).to("cuda")
+            nb = max(2, min(4, (1 << 30) // (8 * b * n)))
+            xs = [x] + [x.clone() for _ in range(nb - 1)]
+            ys = [torch.empty_like(x) for _ in range(nb)]
+            for mode in ("c64", "split_f16", "split_bf16", "f16"):
+                with fftc.Plan(n, b, fftc.FORWARD, mode) as p:
+                    launches(f"{mode} N={n} batch {b}", [p], xs, ys, 3)
+            del x, xs, ys
+            torch.cuda.empty_cache()
+    if "two_pass" in names or "c64_16384" in names:
+        x = torch.from_numpy(synth.uniform_complex(synth.rng(1, 0), (ELEMS,), np.complex64)).to("cuda")
+        xs = [x] + [x.clone() for _ in range(NBUF - 1)]
+        ys = [torch.empty_like(x) for _ in range(NBUF)]
+        for n in ((1 << 20, 65536) if "two_pass" in names else ()) + ((16384,) if "c64_16384" in names else ()):
+            with fftc.Plan(n, ELEMS // n, fftc.FORWARD, "c64") as p:
+                launches(f"c64 N={n} batch {ELEMS // n} ({p.describe()['variant']})", [p], xs, ys, 3)
+        del x, xs, ys
+    if "copy" in names:
+        x = torch.zeros(ELEMS, dtype=torch.complex64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            fftc.copy(x, y, 8 * ELEMS, s)
+        torch.cuda.synchronize()
+        log("profile-set: fftc_copy of 128 MiB done")
+    torch.cuda.empty_cache()
+
+
 def rocpd_summary(paths):
     """Per-kernel call count / mean duration (kernel traces) or mean counter
     value per dispatch (counter runs) from rocprofv3's SQLite output."""
@@ -813,6 +870,9 @@ def main():
 
     torch.cuda.set_device(0)
     timer = Timer(torch)
+    if args.profile_set:
+        profile_set(args.profile_set, torch, fftc, synth)
+        return
     if args.calibrate_copy:
         # a plain copy of known size: 2^24 complex64 = 128 MiB read + 128 MiB written
         x = torch.from_numpy(synth.uniform_complex(synth.rng(1, 0), (ELEMS,), np.complex64)).to("cuda")

@@ -334,7 +334,7 @@ fftc_status fftc_plan_mixed(const int64_t *n, int64_t count, int direction, int 
  * timed by its own events.  A candidate's time is the median of `reps`
  * launches (1 <= reps <= 100000; 20 or more gives stable picks); two
  * candidates tie unless their medians differ by more than twice the larger
- * relative interquartile range of their launches (at least 1%), and ties go
+ * relative interquartile range of their launches (at least 3%), and ties go
  * to fewer stages, then to the larger leading radix.  The winner is recorded
  * in the process's tuning database, which later plans for (n, dtype) use.
  * Returns the chosen list in radices[0..*count) and its median time per

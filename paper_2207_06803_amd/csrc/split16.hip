@@ -5,20 +5,25 @@
 // vec(A X), it is the dense product of the 16 x 16 DFT matrix W with a
 // 16 x (N/16) matrix whose columns are the butterflies.  In real form, for
 // a group of 16 butterflies (columns), with V = Vr + i Vi the twiddled inputs:
-//     Yr = [Wr | -Wi] [Vr; Vi],   Yi = [Wi | Wr] [Vr; Vi]
-// each a 16 x 32 by 32 x 16 product: one MFMA.  Operands are split as
+//     Yr = Wr Vr - Wi Vi,   Yi = Wi Vr + Wr Vi
+// each a 16 x 32 by 32 x 16 product over the stacked real and imaginary
+// parts: one MFMA.  Operands are split as
 // X = X_hi + 2^-s X_lo (X_lo stored scaled by 2^s so it stays normal), and
 //     Y ~ W_hi V_hi + 2^-s (W_hi V_lo + W_lo V_hi)
 // accumulated in FP32 (the split-operand refinement of Markidis et al. 2018
 // and Ootomo & Yokota 2022).  Modes: fp16 hi+lo (s = 11), bf16 hi+lo
 // (s = 8), bf16 hi+mid+lo (three terms, s = 8 per level) and plain fp16.
 //
-// Data path per transform (one workgroup): coalesced load into planar re/im
-// LDS arrays, radix-16 stages LDS -> LDS, an optional final radix-2/4/8
-// stage on the VALU, coalesced store.  Each stage multiplies its outputs by
+// Data path per transform (one workgroup): the first radix-16 stage reads
+// its inputs from HBM (each 16 lanes 128 contiguous bytes), the stages
+// exchange through interleaved complex LDS, and the last stage -- radix 16,
+// or a final radix-2/4/8 stage on the VALU -- writes HBM in natural order.  Each stage multiplies its outputs by
 // the twiddle factors of the next stage (same table layout as the Stockham
-// plans), so MFMA inputs need no complex multiply and each lane reads only
-// the real or the imaginary parts it feeds to the matrix core.
+// plans), so MFMA inputs need no complex multiply.  The contraction index
+// pairs each input's real and imaginary parts (k = 2 r + c), so a lane's
+// eight B values are four whole complex inputs: one 8-byte LDS read per
+// complex element and stage, split once into hi and lo parts, and one 8-byte
+// write of each complex output.
 //
 // MFMA lane layouts (16x16x32, 64 lanes, l = lane):
 //   A[m][k]: m = l % 16, k = 8 (l / 16) + i   (8 values per lane)
@@ -101,7 +106,14 @@ template <int N> constexpr int split_tail() {
     while (m % 16 == 0) m /= 16;
     return m;
 }
-template <int N> constexpr int split_waves() { return N <= 4096 ? (N / 256 < 4 ? (N / 256 < 1 ? 1 : N / 256) : 4) : N / 1024; }
+// Waves per transform: one per group of 16 butterflies up to four (N = 256:
+// 1, 512: 2, 1024 .. 4096: 4), then one per 1024 elements (measured at batch
+// 8192: one wave for N = 1024 holding all four groups took 55 us against
+// 47 us with four).
+__host__ __device__ constexpr int split_waves_for(int64_t n) {
+    return n <= 4096 ? (n / 256 < 4 ? (n / 256 < 1 ? 1 : (int)(n / 256)) : 4) : (int)(n / 1024);
+}
+template <int N> constexpr int split_waves() { return split_waves_for(N); }
 
 __device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
 
@@ -135,9 +147,12 @@ __device__ __forceinline__ void apply_next_twiddle(int p, float& re, float& im, 
 }
 
 // One radix-16 MFMA stage (NS = product of earlier radices).  R2/NS2/TW2
-// describe the next stage (R2 = 0: none).
-template <int N, int MODE, int NS, int R2, int NS2, int TW2, int W>
-__device__ __forceinline__ void mfma_stage(float* re, float* im, const float2* __restrict__ tw,
+// describe the next stage (R2 = 0: none).  The contraction index k runs over
+// (input r, real or imaginary part) as k = 2 r + c, so the lane holding
+// B[k][n], k = 8 (l / 16) + i, takes inputs r = 4 (l / 16) .. + 3 of
+// butterfly n whole: four complex values read from the interleaved LDS.
+template <int N, int MODE, int NS, int R2, int NS2, int TW2, int W, bool INV, bool FIRST, bool LASTG>
+__device__ __forceinline__ void mfma_stage(float2* x, const float2* gin, float2* gout, const float2* __restrict__ tw,
                                            const typename SplitTraits<MODE>::V (&a1)[3],
                                            const typename SplitTraits<MODE>::V (&a2)[3]) {
     using T = SplitTraits<MODE>;
@@ -146,21 +161,22 @@ __device__ __forceinline__ void mfma_stage(float* re, float* im, const float2* _
     constexpr int NB = N / 16;        // butterflies
     constexpr int G = NB / 16;        // groups of 16 butterflies
     constexpr int GPW = (G + W - 1) / W;
+    constexpr bool EVENG = G % W == 0;  // every wave has GPW groups
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const int n = lane & 15, g4 = lane >> 4;
-    const int half = g4 & 1;
-    const float* src = (g4 >= 2) ? im : re;
     V b[GPW][3];
 #pragma unroll
     for (int gi = 0; gi < GPW; ++gi) {
         const int grp = wave + gi * W;
-        if (grp < G) {
+        if (EVENG || grp < G) {
             const int j = grp * 16 + n;
             E parts[8][3];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int r = 8 * half + i;
-                split<MODE>(src[spad(j + r * NB)], parts[i]);
+            for (int i = 0; i < 4; ++i) {
+                // the first stage reads HBM directly (16 lanes: 128 contiguous bytes)
+                const float2 v = FIRST ? ld_in<INV>(gin + j + (4 * g4 + i) * NB) : x[spad(j + (4 * g4 + i) * NB)];
+                split<MODE>(v.x, parts[2 * i]);
+                split<MODE>(v.y, parts[2 * i + 1]);
             }
 #pragma unroll
             for (int t = 0; t < T::TERMS; ++t)
@@ -181,16 +197,16 @@ __device__ __forceinline__ void mfma_stage(float* re, float* im, const float2* _
             const int kk = j % NS, q = j / NS;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                wn[gi][c] = grp < G ? next_twiddle<N, R2, NS2, TW2>(q * NS * 16 + (4 * g4 + c) * NS + kk, tw)
+                wn[gi][c] = (EVENG || grp < G) ? next_twiddle<N, R2, NS2, TW2>(q * NS * 16 + (4 * g4 + c) * NS + kk, tw)
                                     : make_float2(1.f, 0.f);
         }
     }
-    __syncthreads();
+    if constexpr (!FIRST) __syncthreads();  // every read of the LDS before it is overwritten
     const float inv1 = 1.f / T::SCALE, inv2 = inv1 * inv1;
 #pragma unroll
     for (int gi = 0; gi < GPW; ++gi) {
         const int grp = wave + gi * W;
-        if (grp < G) {
+        if (EVENG || grp < G) {
             const f32x4 z = {0.f, 0.f, 0.f, 0.f};
             f32x4 yr0 = mma(a1[0], b[gi][0], z), yi0 = mma(a2[0], b[gi][0], z);
             f32x4 yr1 = z, yi1 = z, yr2 = z, yi2 = z;
@@ -219,17 +235,21 @@ __device__ __forceinline__ void mfma_stage(float* re, float* im, const float2* _
                 } else if constexpr (R2 > 0) {
                     apply_next_twiddle<N, R2, NS2, TW2>(p, vr, vi, tw);
                 }
-                re[spad(p)] = vr;
-                im[spad(p)] = vi;
+                // the last stage writes HBM in natural order (p = m N/16 + j)
+                if constexpr (LASTG)
+                    st_out<INV>(gout + p, make_float2(vr, vi));
+                else
+                    x[spad(p)] = make_float2(vr, vi);
             }
         }
     }
-    __syncthreads();
+    if constexpr (!LASTG) __syncthreads();
 }
 
-// Final radix-RT stage on the VALU (its input twiddles already applied).
-template <int N, int RT, int NS, int NT>
-__device__ __forceinline__ void tail_stage(float* re, float* im) {
+// Final radix-RT stage on the VALU (its input twiddles already applied),
+// writing HBM in natural order.
+template <int N, int RT, int NS, int NT, bool INV>
+__device__ __forceinline__ void tail_stage(float2* x, float2* gout) {
     constexpr int NR = N / RT;
     constexpr int NB = (NR + NT - 1) / NT;
     float2 v[NB][RT];
@@ -239,28 +259,24 @@ __device__ __forceinline__ void tail_stage(float* re, float* im) {
         const int j = t + i * NT;
         if (j < NR) {
 #pragma unroll
-            for (int r = 0; r < RT; ++r) v[i][r] = make_float2(re[spad(j + r * NR)], im[spad(j + r * NR)]);
+            for (int r = 0; r < RT; ++r) v[i][r] = x[spad(j + r * NR)];
             Codelet<RT, float2>::run(v[i]);
         }
     }
-    __syncthreads();
+    static_assert(NS * RT == N, "the tail is the last stage");
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int j = t + i * NT;
         if (j < NR) {
-            const int k = j % NS, base = (j / NS) * NS * RT + k;
 #pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                re[spad(base + r * NS)] = v[i][r].x;
-                im[spad(base + r * NS)] = v[i][r].y;
-            }
+            for (int r = 0; r < RT; ++r) st_out<INV>(gout + j + r * NS, v[i][r]);
         }
     }
-    __syncthreads();
 }
 
-template <int N, int MODE, int S, int NS, int TWOFF, int W>
-__device__ __forceinline__ void run_mfma_stages(float* re, float* im, const float2* __restrict__ tw,
+template <int N, int MODE, int S, int NS, int TWOFF, int W, bool INV>
+__device__ __forceinline__ void run_mfma_stages(float2* x, const float2* gin, float2* gout,
+                                                const float2* __restrict__ tw,
                                                 const typename SplitTraits<MODE>::V (&a1)[3],
                                                 const typename SplitTraits<MODE>::V (&a2)[3]) {
     constexpr int S16 = split_stages16<N>();
@@ -268,15 +284,21 @@ __device__ __forceinline__ void run_mfma_stages(float* re, float* im, const floa
     if constexpr (S < S16) {
         constexpr int TW2 = TWOFF + 15 * NS;  // next stage's twiddle segment
         constexpr int R2 = (S + 1 < S16) ? 16 : (RT > 1 ? RT : 0);
-        mfma_stage<N, MODE, NS, R2, NS * 16, TW2, W>(re, im, tw, a1, a2);
-        run_mfma_stages<N, MODE, S + 1, NS * 16, TW2, W>(re, im, tw, a1, a2);
+        mfma_stage<N, MODE, NS, R2, NS * 16, TW2, W, INV, S == 0, R2 == 0>(x, gin, gout, tw, a1, a2);
+        run_mfma_stages<N, MODE, S + 1, NS * 16, TW2, W, INV>(x, gin, gout, tw, a1, a2);
     } else if constexpr (RT > 1) {
-        tail_stage<N, RT, NS, 64 * W>(re, im);
+        tail_stage<N, RT, NS, 64 * W, INV>(x, gout);
     }
 }
 
+// Four-wave transforms (N = 1024 .. 4096) of the two-term modes are compiled
+// for four resident workgroups per CU, the most their LDS allows (N = 4096,
+// split fp16: 137 VGPRs + 16 AGPRs and three workgroups without the bound,
+// 116 VGPRs with it: 155 -> 135 us at batch 8192; the three-term mode spills
+// under it).
+template <int MODE> constexpr bool split_bound4() { return MODE != FFTC_C64_SPLIT3_BF16; }
 template <int N, int MODE, bool INV>
-__global__ void __launch_bounds__(64 * split_waves<N>())
+__global__ void __launch_bounds__(64 * split_waves<N>(), (split_waves<N>() == 4 && split_bound4<MODE>()) ? 4 : 1)
 split_fft(const float2* in, float2* out, const float2* __restrict__ tw, int64_t batch) {
     using T = SplitTraits<MODE>;
     using V = typename T::V;
@@ -284,24 +306,25 @@ split_fft(const float2* in, float2* out, const float2* __restrict__ tw, int64_t 
     constexpr int W = split_waves<N>();
     constexpr int NT = 64 * W;
     constexpr int L = lds_len(N);
-    __shared__ float re[L], im[L];
+    __shared__ float2 xs[L];
     const int64_t b = blockIdx.x;
     const float2* x = in + b * N;
     float2* y = out + b * N;
     const int t = (int)threadIdx.x;
-    // operands A1 = [Wr | -Wi], A2 = [Wi | Wr] for this lane, split
+    // operands A1 = [Wr | -Wi], A2 = [Wi | Wr] for this lane, split, with the
+    // contraction index k = 2 r + c (c = 0: real parts, 1: imaginary parts)
     V a1[3], a2[3];
     {
         const int lane = t & 63, m = lane & 15, g4 = lane >> 4;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const int k = 8 * g4 + i, col = k & 15;
+            const int k = 8 * g4 + i, col = k >> 1;
             float c, s;
             w16((m * col) & 15, &c, &s);
             // W[m][col] = cos - i sin
             const float wr = c, wi = -s;
-            const float v1 = (k < 16) ? wr : -wi;
-            const float v2 = (k < 16) ? wi : wr;
+            const float v1 = (k & 1) ? -wi : wr;
+            const float v2 = (k & 1) ? wr : wi;
             E p1[3], p2[3];
             split<MODE>(v1, p1);
             split<MODE>(v2, p2);
@@ -312,24 +335,8 @@ split_fft(const float2* in, float2* out, const float2* __restrict__ tw, int64_t 
             }
         }
     }
-    // coalesced load into planar LDS
-    constexpr int IT = (N + NT - 1) / NT;
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        const int e = t + i * NT;
-        if (e < N) {
-            float2 v = ld_in<INV>(x + e);
-            re[spad(e)] = v.x;
-            im[spad(e)] = v.y;
-        }
-    }
-    __syncthreads();
-    run_mfma_stages<N, MODE, 0, 1, 0, W>(re, im, tw, a1, a2);
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        const int e = t + i * NT;
-        if (e < N) st_out<INV>(y + e, make_float2(re[spad(e)], im[spad(e)]));
-    }
+    // the first stage reads HBM and the last writes it
+    run_mfma_stages<N, MODE, 0, 1, 0, W, INV>(xs, x, y, tw, a1, a2);
 }
 
 // ---------------------------------------------------------------------------
@@ -369,7 +376,7 @@ std::vector<int> split_radices(int64_t n) {
     return rs;
 }
 
-int split_threads(int64_t n) { return 64 * (n <= 4096 ? (n / 256 < 4 ? (n / 256 < 1 ? 1 : (int)(n / 256)) : 4) : (int)(n / 1024)); }
+int split_threads(int64_t n) { return 64 * split_waves_for(n); }
 
 fftc_status launch_split(const fftc_plan_s* p, const void* in, void* out, int64_t batch, hipStream_t s) {
     const bool inv = p->direction == FFTC_INVERSE;
