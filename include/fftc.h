@@ -381,12 +381,21 @@ fftc_status fftc_order_entry(int dtype, int i, int64_t *n, int *order, int *radi
 fftc_status fftc_autotune_orders(int64_t n, int64_t batch, int dtype, int reps, int *orders, int *radices,
                                  double *us, int max, int *count, int *best);
 
-/* Tuning database persistence (text, one line per (arch, dtype, n)).  The
- * database is also read once from the file named by FFTC_TUNE_DB, if set.
+/* Tuning database persistence (the planner's memory of what was fastest,
+ * Section VI; FFTW's wisdom is the model the paper cites, Section III).
+ * Text, one line per entry:
+ *   <arch> <toolchain> <c64|c128> <n> [<order>:]<r1,r2,...> <ms>
+ * keyed on the device architecture and the HIP version the library's kernels
+ * were compiled with (fftc_tune_key(), e.g. "gfx950 hip7.2.53211"); lines
+ * with another key or in another format are skipped.  The database is read
+ * once from the file named by the FFTC_TUNE_DB environment variable, if set,
+ * and from fftc_server_config.tune_db when a server starts.
  * fftc_tune_load merges the file's entries (*entries = lines accepted). */
 fftc_status fftc_tune_load(const char *path, int *entries);
 fftc_status fftc_tune_save(const char *path, int *entries);
 fftc_status fftc_tune_clear(void);
+/* "<arch> <toolchain>" of this build (static storage). */
+const char *fftc_tune_key(void);
 
 /* ---------------------------------------------------------------------------
  * Serving.  One process-global server takes FFT requests of any supported
@@ -394,8 +403,21 @@ fftc_status fftc_tune_clear(void);
  * requests are admitted in arrival order as device memory (a budget arena
  * for outputs) and in-flight slots free up, each admitted request is launched
  * at once on a stream of a pool so it overlaps with work already on the GPU,
- * and plans with their twiddle tables stay resident between requests.
+ * and plans with their twiddle tables stay resident between requests (the
+ * paper's point that an FFT is compiled once and run many times, Section
+ * VI; the just-in-time flexibility of its JIT mode over a fixed-size AOT
+ * build, Section IV-B, comes from the plan cache: any supported n is served).
+ *
+ * Failure hooks (environment): FFTC_FAULT=k makes the k-th device or arena
+ * allocation from then on fail with FFTC_ERR_OUT_OF_MEMORY before any HIP
+ * call (a failed arena allocation fails that request only; the server keeps
+ * serving), FFTC_LOG=1 logs plans, server start/stop and injected faults to
+ * stderr.  fftc_fault_set(k) sets the same counter from code (k <= 0: off).
  * ------------------------------------------------------------------------- */
+fftc_status fftc_fault_set(int64_t k);
+/* Allocations counted since the last fftc_fault_set (or FFTC_FAULT). */
+int64_t fftc_fault_count(void);
+
 enum { FFTC_EXECUTOR_GPU = 0, FFTC_EXECUTOR_MOCK = 1 };
 
 typedef struct {
@@ -410,6 +432,9 @@ typedef struct {
                               dtype) run as one launch (up to 16 per launch) when the
                               length has a several-requests kernel (powers of two with
                               the preferred radix list); 0: one launch per request */
+    const char *tune_db;   /* tuning database file merged into the process's database
+                              before any plan is made (NULL or "": none; a file that
+                              cannot be read fails the start with FFTC_ERR_INVALID_ARG) */
 } fftc_server_config;
 
 typedef struct {
@@ -435,6 +460,9 @@ typedef struct {
     size_t budget_bytes, bytes_in_use, peak_bytes;
     int pending, inflight, max_inflight_seen;
     int64_t fused_launches, fused_requests;  /* several-requests launches and the requests they ran */
+    size_t plan_bytes;     /* device memory of the resident plans (twiddle tables), on
+                              top of the budget: at most 16 bytes per element of each
+                              distinct (n, direction, dtype) served */
 } fftc_server_stats;
 
 /* Monotonic clock (ns) used for all server timestamps. */

@@ -1,8 +1,11 @@
 // C ABI: plans, execution, errors.  No exception crosses this boundary.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -26,6 +29,53 @@ fftc_status fail_hip(hipError_t e, const char* what) {
 }
 
 void clear_error() { t_last_error.clear(); }
+
+// ---- fault injection and logging -------------------------------------------
+static std::once_flag g_env_once;
+static std::atomic<int64_t> g_fault_at{0}, g_alloc_count{0};
+static std::atomic<bool> g_log{false};
+
+static void read_env() {
+    std::call_once(g_env_once, [] {
+        if (const char* f = getenv("FFTC_FAULT")) g_fault_at = atoll(f);
+        if (const char* l = getenv("FFTC_LOG")) g_log = *l && strcmp(l, "0") != 0;
+    });
+}
+
+bool log_on() {
+    read_env();
+    return g_log.load(std::memory_order_relaxed);
+}
+
+void log_line(const char* fmt, ...) {
+    if (!log_on()) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "fftc: %s\n", buf);
+}
+
+bool fault_hit() {
+    read_env();
+    const int64_t at = g_fault_at.load();
+    if (at <= 0) return false;
+    const bool hit = g_alloc_count.fetch_add(1) + 1 == at;
+    if (hit) log_line("injected allocation failure (allocation %lld)", (long long)at);
+    return hit;
+}
+
+fftc_status dev_malloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (fault_hit()) return fail(FFTC_ERR_OUT_OF_MEMORY, std::string(what) + ": injected allocation failure");
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail_hip(e, what);
+    }
+    return FFTC_OK;
+}
 
 fftc_status enable_large_lds();
 int two_pass_cols(int dtype);
@@ -83,7 +133,8 @@ static fftc_status shape_single(fftc_plan_s* p, const std::vector<int>& rs) {
 static fftc_status alloc_tables(fftc_plan_s* p, const std::vector<TwSegment>& segs, int64_t entries) {
     const size_t cs = csize_of(p->dtype);
     p->tw_bytes = (size_t)std::max<int64_t>(entries, 1) * cs;
-    FFTC_HIP_TRY(hipMalloc(&p->tw, p->tw_bytes));
+    fftc_status st = dev_malloc(&p->tw, p->tw_bytes, "hipMalloc(twiddles)");
+    if (st != FFTC_OK) return st;
     return make_twiddles(p->tw, p->dtype, segs, nullptr);
 }
 
@@ -269,14 +320,20 @@ static fftc_status plan_impl(int64_t n, int64_t batch, int direction, int dtype,
     if (st == FFTC_OK) st = alloc_tables(p, segs, entries);
     if (st == FFTC_OK && p->variant == FFTC_VARIANT_TWO_PASS && !t_plan_no_scratch) {
         p->scratch_bytes = (size_t)batch * (size_t)n * csize_of(dtype);
-        hipError_t e = hipMalloc(&p->scratch, p->scratch_bytes);
-        if (e != hipSuccess) st = fail_hip(e, "hipMalloc(two-pass scratch)");
+        st = dev_malloc(&p->scratch, p->scratch_bytes, "hipMalloc(two-pass scratch)");
     }
     if (st != FFTC_OK) {
         std::string keep = t_last_error;
         fftc_destroy_plan(p);
         t_last_error = keep;
         return st;
+    }
+    if (log_on()) {
+        std::string rs;
+        for (int r : p->radices) rs += (rs.empty() ? "" : ",") + std::to_string(r);
+        log_line("plan n=%lld batch=%lld %s dtype=%d variant=%d radices=%s tables=%zu B scratch=%zu B",
+                 (long long)n, (long long)batch, direction == FFTC_INVERSE ? "inverse" : "forward", dtype,
+                 p->variant, rs.c_str(), p->tw_bytes, p->scratch_bytes);
     }
     *out = p;
     return FFTC_OK;
@@ -307,6 +364,15 @@ const char* fftc_status_string(fftc_status s) {
 }
 
 const char* fftc_last_error(void) { return t_last_error.c_str(); }
+
+fftc_status fftc_fault_set(int64_t k) {
+    read_env();
+    g_fault_at = k > 0 ? k : 0;
+    g_alloc_count = 0;
+    return FFTC_OK;
+}
+
+int64_t fftc_fault_count(void) { return g_alloc_count.load(); }
 
 fftc_status fftc_plan(int64_t n, int64_t batch, int direction, int dtype, fftc_plan_t* plan_out) {
     try {
@@ -635,8 +701,7 @@ fftc_status fftc_plan_layout(int64_t n, int64_t batch, int direction, int dtype,
         st = alloc_tables(p, segs, entries);
         if (st == FFTC_OK && p->col1) {
             p->scratch_bytes = (size_t)batch * (size_t)n * csize_of(dtype);
-            hipError_t he = hipMalloc(&p->scratch, p->scratch_bytes);
-            if (he != hipSuccess) st = fail_hip(he, "hipMalloc(column scratch)");
+            st = dev_malloc(&p->scratch, p->scratch_bytes, "hipMalloc(column scratch)");
         }
         if (st != FFTC_OK) {
             std::string keep = t_last_error;

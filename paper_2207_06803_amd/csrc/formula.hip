@@ -421,24 +421,21 @@ fftc_status formula_prepare(const FormulaProgram& prog, int dtype, int64_t batch
         k = e;
     }
     *kernels = (int)fx->steps.size();
-    fftc_status st = FFTC_OK;
     // (scratch: every execution but a single LDS run may need a second buffer)
-    hipError_t e = hipMalloc(&fx->dev, sizeof(FPass) * fx->host.size());
-    if (e == hipSuccess)
-        e = hipMemcpy(fx->dev, fx->host.data(), sizeof(FPass) * fx->host.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) st = fail_hip(e, "formula pass list");
-    *table_bytes = (size_t)std::max<int64_t>(prog.table_entries, 1) * cs;
+    hipError_t e = hipSuccess;
+    fftc_status st = dev_malloc((void**)&fx->dev, sizeof(FPass) * fx->host.size(), "hipMalloc(formula passes)");
     if (st == FFTC_OK) {
-        e = hipMalloc(&fx->tw, *table_bytes);
-        if (e != hipSuccess) st = fail_hip(e, "hipMalloc(formula tables)");
+        e = hipMemcpy(fx->dev, fx->host.data(), sizeof(FPass) * fx->host.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) st = fail_hip(e, "formula pass list");
     }
+    *table_bytes = (size_t)std::max<int64_t>(prog.table_entries, 1) * cs;
+    if (st == FFTC_OK) st = dev_malloc(&fx->tw, *table_bytes, "hipMalloc(formula tables)");
     if (st == FFTC_OK) st = make_twiddles(fx->tw, dtype, prog.tables, nullptr);
     *scratch_bytes = 0;
     const bool one_lds = fx->steps.size() == 1 && fx->steps[0].lds;
     if (st == FFTC_OK && !one_lds) {
         *scratch_bytes = (size_t)batch * (size_t)prog.dim * cs;
-        e = hipMalloc(&fx->scratch, *scratch_bytes);
-        if (e != hipSuccess) st = fail_hip(e, "hipMalloc(formula scratch)");
+        st = dev_malloc(&fx->scratch, *scratch_bytes, "hipMalloc(formula scratch)");
     }
     if (st == FFTC_OK) {
         // per kernel, not per plan: allow the largest tile any plan uses

@@ -19,6 +19,18 @@ void clear_error();
 // A launch's workgroup count must fit the grid's x dimension.
 inline bool grid_fits(int64_t groups) { return groups >= 0 && groups <= 0x7fffffff; }
 
+// Every device allocation of the library goes through dev_malloc, and every
+// allocation of the serving arena asks fault_hit first: with FFTC_FAULT=k in
+// the environment (or fftc_fault_set(k)) the k-th such allocation counted
+// from then fails as out of memory before any HIP call, so failure paths can
+// be tested on purpose (on a CPU with the mock executor).
+bool fault_hit();
+fftc_status dev_malloc(void** p, size_t bytes, const char* what);
+// FFTC_LOG=1 in the environment: one line per plan, server start and stop
+// and injected fault on stderr.
+bool log_on();
+void log_line(const char* fmt, ...);
+
 #define FFTC_HIP_TRY(call)                                   \
     do {                                                     \
         hipError_t e_ = (call);                              \
@@ -44,6 +56,8 @@ void tune_record(int64_t n, int dtype, const std::vector<int>& rs, double ms);
 bool tune_lookup_order(int64_t n, int dtype, int* order, int* radix);
 void tune_record_order(int64_t n, int dtype, int order, int radix, double ms);
 int tune_load_file(const char* path);
+// "<arch> <toolchain>": the part of a database line that must match.
+const char* tune_key();
 int tune_save_file(const char* path);
 void tune_clear_all();
 

@@ -172,7 +172,10 @@ fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count) {
     const size_t o_offs = align(o_wg + sizeof(int) * wg_start.size());
     const size_t o_tw = align(o_offs + sizeof(int64_t) * toffs.size());
     const size_t bytes = o_tw + (size_t)std::max<int64_t>(twoff, 1) * cs;
-    FFTC_HIP_TRY(hipMalloc(&m->dev, bytes));
+    {
+        fftc_status sa = dev_malloc(&m->dev, bytes, "hipMalloc(mixed plan tables)");
+        if (sa != FFTC_OK) return sa;
+    }
     m->dev_bytes = bytes;
     char* base = static_cast<char*>(m->dev);
     m->d_classes = reinterpret_cast<MixedClass*>(base + o_cls);

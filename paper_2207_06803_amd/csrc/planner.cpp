@@ -133,10 +133,14 @@ std::vector<int> choose_radices(int64_t n, int dtype) {
 }
 
 // ---- tuning database ----------------------------------------------------------
-// Text file, one line per entry:  <arch> <c64|c128> <n> [<order>:]<r1,r2,...> <ms>
-// with <order> "ct", "pease" or "fourstep" for an alternative order (its list is the
-// radix repeated), none for Stockham.  Entries for another architecture are
-// ignored; a list that does not multiply to n is ignored.
+// Text file, one line per entry:
+//   <arch> <toolchain> <c64|c128> <n> [<order>:]<r1,r2,...> <ms>
+// with <toolchain> the HIP version the library's kernels were compiled with
+// ("hip7.2.53211"): timings hold for one device and one compiler's code.
+// <order> is "ct", "pease" or "fourstep" for an alternative order (its list is
+// the radix repeated), none for Stockham.  Lines for another architecture or
+// toolchain, lines in another format, and lists that do not multiply to n are
+// ignored.
 namespace {
 struct TuneEntry {
     std::vector<int> rs;
@@ -147,16 +151,22 @@ std::mutex g_tune_mu;
 std::map<std::pair<int64_t, int>, TuneEntry> g_tune;
 bool g_tune_env_done = false;
 const char* kTuneArch = "gfx950";
+#define FFTC_STR2(x) #x
+#define FFTC_STR(x) FFTC_STR2(x)
+const char* kTuneToolchain = "hip" FFTC_STR(HIP_VERSION_MAJOR) "." FFTC_STR(HIP_VERSION_MINOR) "." FFTC_STR(
+    HIP_VERSION_PATCH);
 
 int load_locked(const char* path) {
     FILE* f = fopen(path, "r");
     if (!f) return -1;
-    char arch[64], dt[16], rl[256];
+    char line[512], arch[64], tc[64], dt[16], rl[256], extra[8];
     long long n;
     double ms;
     int added = 0;
-    while (fscanf(f, "%63s %15s %lld %255s %lf", arch, dt, &n, rl, &ms) == 5) {
-        if (strcmp(arch, kTuneArch) != 0) continue;
+    while (fgets(line, sizeof line, f)) {
+        if (sscanf(line, "%63s %63s %15s %lld %255s %lf %7s", arch, tc, dt, &n, rl, &ms, extra) != 6) continue;
+        if (strcmp(arch, kTuneArch) != 0 || strcmp(tc, kTuneToolchain) != 0) continue;
+        if (strcmp(dt, "c64") != 0 && strcmp(dt, "c128") != 0) continue;
         const int dtype = strcmp(dt, "c128") == 0 ? FFTC_C128 : FFTC_C64;
         int order = 0;
         char* list = rl;
@@ -168,12 +178,13 @@ int load_locked(const char* path) {
         if (order < 0) continue;
         std::vector<int> rs;
         int64_t prod = 1;
-        bool ok = true;
-        for (char* tok = strtok(list, ","); tok; tok = strtok(nullptr, ",")) {
+        bool ok = n > 1;
+        for (char* tok = strtok(list, ","); tok && ok; tok = strtok(nullptr, ",")) {
             const int r = atoi(tok);
             ok = ok && (r == 2 || r == 3 || r == 4 || r == 5 || r == 7 || r == 8 || r == 16);
             rs.push_back(r);
             prod *= r;
+            ok = ok && prod <= n;
         }
         if (order > 0) {  // one radix repeated
             for (int r : rs) ok = ok && r == rs[0];
@@ -240,7 +251,7 @@ int tune_save_file(const char* path) {
     FILE* f = fopen(path, "w");
     if (!f) return -1;
     for (auto& kv : g_tune) {
-        fprintf(f, "%s %s %lld ", kTuneArch, kv.first.second == FFTC_C128 ? "c128" : "c64",
+        fprintf(f, "%s %s %s %lld ", kTuneArch, kTuneToolchain, kv.first.second == FFTC_C128 ? "c128" : "c64",
                 (long long)kv.first.first);
         if (kv.second.order)
             fprintf(f, "%s:", kv.second.order == 1 ? "ct" : kv.second.order == 2 ? "pease" : "fourstep");
@@ -250,6 +261,11 @@ int tune_save_file(const char* path) {
     }
     fclose(f);
     return (int)g_tune.size();
+}
+
+const char* tune_key() {
+    static const std::string key = std::string(kTuneArch) + " " + kTuneToolchain;
+    return key.c_str();
 }
 
 void tune_clear_all() {

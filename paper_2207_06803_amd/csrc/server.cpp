@@ -2,8 +2,8 @@
 // taken as they arrive and run with continuous batching on one GPU.
 //
 //  - Plans (and their twiddle tables) stay resident, one per (n, direction,
-//    dtype), sized for the largest batch seen; requests run the first `batch`
-//    transforms of the plan.
+//    dtype), built once for the largest batch the budget can hold; requests
+//    run the first `batch` transforms of the plan.
 //  - Outputs come from one device arena of `budget_bytes` (first fit with
 //    coalescing, 256-byte granules).  A request is admitted in arrival order
 //    when its output fits in the free arena and an in-flight slot is free;
@@ -130,9 +130,12 @@ class Server {
         stats_.budget_bytes = arena_.cap();
         fused_launches_ = 0;
         fused_requests_ = 0;
+        if (cfg_.tune_db && *cfg_.tune_db && tune_load_file(cfg_.tune_db) < 0)
+            return fail(FFTC_ERR_INVALID_ARG, std::string("cannot read tune_db ") + cfg_.tune_db);
         if (!mock_) {
             FFTC_HIP_TRY(hipGetDevice(&device_));
-            FFTC_HIP_TRY(hipMalloc(&base_, std::max<size_t>(arena_.cap(), kGranule)));
+            fftc_status sa = dev_malloc(&base_, std::max<size_t>(arena_.cap(), kGranule), "hipMalloc(server arena)");
+            if (sa != FFTC_OK) return sa;
             // touch the whole arena once now (about 13 ms for 64 GiB), so no
             // request pays the first use of its pages
             FFTC_HIP_TRY(hipMemset(base_, 0, std::max<size_t>(arena_.cap(), kGranule)));
@@ -149,6 +152,8 @@ class Server {
         stop_ = false;
         drain_ = true;
         th_ = std::thread([this] { loop(); });
+        log_line("server start: budget %zu B, %d streams, %d in flight, %s executor, fuse %d", arena_.cap(),
+                 cfg_.n_streams, cfg_.max_inflight, mock_ ? "mock" : "GPU", cfg_.fuse);
         return FFTC_OK;
     }
 
@@ -163,7 +168,8 @@ class Server {
         const size_t bytes = (size_t)n * elem_bytes(dtype);
         void* buf = nullptr;
         hipStream_t s = nullptr;
-        FFTC_HIP_TRY(hipMalloc(&buf, 2 * bytes));
+        st = dev_malloc(&buf, 2 * bytes, "hipMalloc(prepare buffer)");
+        if (st != FFTC_OK) return st;
         hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipMemsetAsync(buf, 0, 2 * bytes, s);
         if (e == hipSuccess) {
@@ -236,6 +242,7 @@ class Server {
     // outputs must be released by the client meanwhile if memory is short),
     // else they complete with FFTC_ERR_SHUTDOWN.  Waits for the GPU work.
     fftc_status stop(bool drain) {
+        log_line("server stop (%s)", drain ? "drain" : "cancel queued");
         {
             std::lock_guard<std::mutex> g(mu_);
             stop_ = true;
@@ -248,9 +255,7 @@ class Server {
         {
             std::lock_guard<std::mutex> g(plan_mu_);
             for (auto& kv : plans_) fftc_destroy_plan(kv.second);
-            for (auto p : retired_) fftc_destroy_plan(p);
             plans_.clear();
-            retired_.clear();
         }
         if (!mock_) {
             for (auto e : events_) (void)hipEventDestroy(e);
@@ -272,30 +277,33 @@ class Server {
         stats_.inflight = running_count_;
         stats_.fused_launches = fused_launches_.load();
         stats_.fused_requests = fused_requests_.load();
+        stats_.plan_bytes = plan_bytes_.load();
         *s = stats_;
     }
 
    private:
-    // plan cache; plan_mu_ held
+    // plan cache; plan_mu_ held.  One plan per (n, direction, dtype), built
+    // for the largest batch the budget can hold (a longer request is refused
+    // at submit), so no request ever needs a bigger one: a plan's device
+    // memory (its twiddle tables; the server never runs in place, so no
+    // scratch) does not depend on its batch.
     fftc_status get_plan(int64_t n, int direction, int dtype, int64_t batch, fftc_plan_t* out) {
         const auto key = std::make_tuple(n, direction, dtype);
         auto it = plans_.find(key);
-        if (it != plans_.end() && it->second->batch >= batch) {
+        if (it != plans_.end()) {
+            if (it->second->batch < batch) return fail(FFTC_ERR_TOO_LARGE, "request batch beyond the budget");
             *out = it->second;
             return FFTC_OK;
         }
-        const int64_t cap = std::max<int64_t>(batch, it != plans_.end() ? it->second->batch : 0);
+        int64_t cap = (int64_t)(arena_.cap() / ((size_t)n * elem_bytes(dtype)));
+        cap = std::min<int64_t>(std::max<int64_t>({cap, batch, 1}), std::min<int64_t>((int64_t(1) << 40) / n, 0x7fffffff));
         fftc_plan_t p = nullptr;
         t_plan_no_scratch = true;  // the server never runs in place
-        fftc_status st = fftc_plan(n, std::max<int64_t>(cap, 1), direction, dtype, &p);
+        fftc_status st = fftc_plan(n, cap, direction, dtype, &p);
         t_plan_no_scratch = false;
         if (st != FFTC_OK) return st;
-        if (it != plans_.end()) {
-            retired_.push_back(it->second);  // may still be in flight; freed at stop
-            it->second = p;
-        } else {
-            plans_[key] = p;
-        }
+        plans_[key] = p;
+        plan_bytes_ += p->tw_bytes + p->scratch_bytes;
         *out = p;
         return FFTC_OK;
     }
@@ -443,6 +451,20 @@ class Server {
                 // admission in arrival order: the head waits for room
                 while (!pending_.empty() && !free_slots.empty()) {
                     size_t off = 0;
+                    if (fault_hit()) {  // an injected allocation failure fails this request only
+                        fftc_completion c{};
+                        c.tag = pending_.front().r.tag;
+                        c.status = FFTC_ERR_OUT_OF_MEMORY;
+                        c.arrival_ns = pending_.front().r.arrival_ns;
+                        c.admit_ns = c.start_ns = c.done_ns = now_ns();
+                        c.n = pending_.front().r.n;
+                        c.batch = pending_.front().r.batch;
+                        pending_.pop_front();
+                        done_.push_back(c);
+                        ++stats_.completed;
+                        ++stats_.failed;
+                        continue;
+                    }
                     if (!arena_.alloc(pending_.front().bytes, &off)) break;
                     InFlight f{};
                     f.stream = -1;
@@ -558,7 +580,7 @@ class Server {
     std::deque<fftc_completion> done_;
     std::unordered_map<void*, std::pair<size_t, size_t>> live_;
     std::map<std::tuple<int64_t, int, int>, fftc_plan_t> plans_;
-    std::vector<fftc_plan_t> retired_;
+    std::atomic<size_t> plan_bytes_{0};  // device memory of the resident plans
     fftc_server_stats stats_{};
     std::atomic<int64_t> fused_launches_{0}, fused_requests_{0};  // written by the dispatcher only
     std::atomic<uint64_t> wakes_{0};  // submits, releases and stops, for the dispatcher's idle poll

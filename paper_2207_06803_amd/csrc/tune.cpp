@@ -40,8 +40,9 @@ int64_t tune_batch(int64_t n, int64_t batch) { return std::max(batch, (kTuneMinE
 fftc_status alloc_buffers(DeviceBuffers& b, size_t bytes, int reps) {
     FFTC_HIP_TRY(hipStreamCreate(&b.s));
     for (int i = 0; i < kTunePairs; ++i) {
-        FFTC_HIP_TRY(hipMalloc(&b.in[i], bytes));
-        FFTC_HIP_TRY(hipMalloc(&b.out[i], bytes));
+        fftc_status st = dev_malloc(&b.in[i], bytes, "hipMalloc(autotune input)");
+        if (st == FFTC_OK) st = dev_malloc(&b.out[i], bytes, "hipMalloc(autotune output)");
+        if (st != FFTC_OK) return st;
         FFTC_HIP_TRY(hipMemsetAsync(b.in[i], 0x3c, bytes, b.s));  // small finite values
     }
     b.ev.assign(reps + 1, nullptr);
@@ -216,6 +217,8 @@ fftc_status fftc_tune_save(const char* path, int* entries) {
     if (entries) *entries = k;
     return FFTC_OK;
 }
+
+const char* fftc_tune_key(void) { return tune_key(); }
 
 fftc_status fftc_tune_clear(void) {
     tune_clear_all();

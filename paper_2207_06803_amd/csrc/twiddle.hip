@@ -39,7 +39,10 @@ fftc_status make_twiddles(void* table, int dtype, const std::vector<TwSegment>& 
     }
     if (segs.size() > 65535) return fail(FFTC_ERR_INTERNAL, "too many twiddle segments");
     TwSegDev* d = nullptr;
-    FFTC_HIP_TRY(hipMalloc(&d, sizeof(TwSegDev) * h.size()));
+    {
+        fftc_status st = dev_malloc((void**)&d, sizeof(TwSegDev) * h.size(), "hipMalloc(twiddle segments)");
+        if (st != FFTC_OK) return st;
+    }
     hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(TwSegDev) * h.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) {
         const int block = 256;

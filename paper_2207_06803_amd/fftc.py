@@ -96,6 +96,7 @@ _SIGNATURES = {
     "fftc_tune_load": (_int, [ctypes.c_char_p, ctypes.POINTER(_int)]),
     "fftc_tune_save": (_int, [ctypes.c_char_p, ctypes.POINTER(_int)]),
     "fftc_tune_clear": (_int, []),
+    "fftc_tune_key": (ctypes.c_char_p, []),
     "fftc_plan_formula": (_int, [ctypes.c_char_p, _i64, _int, _int, _int, ctypes.POINTER(_vp)]),
     "fftc_formula_lower": (_int, [ctypes.c_char_p, _int, _int, ctypes.POINTER(_i64), ctypes.c_char_p,
                                   ctypes.c_size_t]),
@@ -453,6 +454,11 @@ def tune_save(path: str) -> int:
     k = _int()
     check(lib.fftc_tune_save(path.encode(), ctypes.byref(k)), "fftc_tune_save")
     return k.value
+
+
+def tune_key() -> str:
+    """'<arch> <toolchain>' that a tuning-database line must start with."""
+    return lib.fftc_tune_key().decode()
 
 
 def tune_clear() -> None:

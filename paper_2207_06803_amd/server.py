@@ -12,7 +12,7 @@ EXECUTOR_MOCK = 1
 
 class Config(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("n_streams", _int), ("max_inflight", _int),
-                ("executor", _int), ("mock_ns_per_mb", _i64), ("fuse", _int)]
+                ("executor", _int), ("mock_ns_per_mb", _i64), ("fuse", _int), ("tune_db", ctypes.c_char_p)]
 
 
 class Request(ctypes.Structure):
@@ -30,7 +30,7 @@ class Stats(ctypes.Structure):
                 ("cancelled", _i64), ("failed", _i64), ("budget_bytes", ctypes.c_size_t),
                 ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("pending", _int),
                 ("inflight", _int), ("max_inflight_seen", _int), ("fused_launches", _i64),
-                ("fused_requests", _i64)]
+                ("fused_requests", _i64), ("plan_bytes", ctypes.c_size_t)]
 
 
 fftc.register("fftc_now_ns", _i64, [])
@@ -41,6 +41,8 @@ fftc.register("fftc_poll", _int, [ctypes.POINTER(Completion), _int, ctypes.POINT
 fftc.register("fftc_release", _int, [_vp])
 fftc.register("fftc_server_stats_get", _int, [ctypes.POINTER(Stats)])
 fftc.register("fftc_server_stop", _int, [_int])
+fftc.register("fftc_fault_set", _int, [_i64])
+fftc.register("fftc_fault_count", _i64, [])
 
 lib = fftc.lib
 
@@ -50,9 +52,19 @@ def now_ns() -> int:
 
 
 def start(budget_bytes: int, n_streams: int = 4, max_inflight: int = 64,
-          executor: int = EXECUTOR_GPU, mock_ns_per_mb: int = 0, fuse: bool = False) -> None:
-    cfg = Config(budget_bytes, n_streams, max_inflight, executor, mock_ns_per_mb, 1 if fuse else 0)
+          executor: int = EXECUTOR_GPU, mock_ns_per_mb: int = 0, fuse: bool = False, tune_db: str = None) -> None:
+    cfg = Config(budget_bytes, n_streams, max_inflight, executor, mock_ns_per_mb, 1 if fuse else 0,
+                 tune_db.encode() if tune_db else None)
     check(lib.fftc_server_start(ctypes.byref(cfg)), "fftc_server_start")
+
+
+def fault_set(k: int) -> None:
+    """Fail the k-th device or arena allocation from now on (k <= 0: off)."""
+    check(lib.fftc_fault_set(int(k)), "fftc_fault_set")
+
+
+def fault_count() -> int:
+    return int(lib.fftc_fault_count())
 
 
 def prepare(n: int, direction: int, dtype="c64", max_batch: int = 1) -> None:

@@ -46,7 +46,7 @@ def test_autotune_orders_and_recorded_order(tmp_path):
         say("orders at 1024:", res, "best", best)
         # a recorded order is what fftc_plan runs
         db = tmp_path / "db.txt"
-        db.write_text("gfx950 c64 256 pease:16,16 0.01\n")
+        db.write_text(f"{fftc.tune_key()} c64 256 pease:16,16 0.01\n")
         assert fftc.tune_load(str(db)) == 1
         x = synth.uniform_complex(synth.rng(141), (9, 256), np.complex64)
         with fftc.Plan(256, 9, FWD, "c64") as p:

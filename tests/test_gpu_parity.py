@@ -251,3 +251,24 @@ def test_unusable_tensors_refused_before_launch():
     with pytest.raises(fftc.FFTCError):
         fftc.copy(big, y[: n - 2], 8 * n)                                    # destination too short
     torch.cuda.synchronize()
+
+
+def test_injected_device_allocation_faults():
+    """FFTC_FAULT's counter from code: the k-th device allocation of a plan
+    fails with FFTC_ERR_OUT_OF_MEMORY before any HIP call, the partial plan
+    is freed, and the next plan works."""
+    from paper_2207_06803_amd import server as srv
+    free0 = torch.cuda.mem_get_info()[0]
+    try:
+        for n, k in ((1024, 1), (1 << 20, 1), (1 << 20, 2), (1 << 20, 3)):
+            srv.fault_set(k)
+            with pytest.raises(fftc.FFTCError) as e:
+                fftc.Plan(n, 4, FWD, "c64")
+            assert e.value.status == 3 and "injected" in str(e.value), (n, k)
+        srv.fault_set(0)
+        with fftc.Plan(1 << 20, 4, FWD, "c64") as p:
+            assert p.describe()["variant"] == "two_pass"
+        torch.cuda.synchronize()
+        assert abs(torch.cuda.mem_get_info()[0] - free0) < (64 << 20)
+    finally:
+        srv.fault_set(0)

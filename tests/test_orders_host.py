@@ -42,13 +42,14 @@ def test_plan_order_errors():
 def test_tuning_db_order_lines(tmp_path):
     fftc.tune_clear()
     src = tmp_path / "in.txt"
-    src.write_text("gfx950 c64 1024 pease:4,4,4,4,4 0.05\n"
-                   "gfx950 c64 256 foo:2,2,2,2,2,2,2,2 0.1\n"      # unknown order
-                   "gfx950 c64 4096 ct:4,4 0.1\n"                  # does not multiply to n
-                   "gfx950 c64 512 ct:2,2,2,2,2,2,2,2,2 0.1\n"     # not compiled
-                   "gfx950 c128 64 ct:8,8 0.01\n"
-                   "gfx950 c128 4096 fourstep:16,16,16 0.03\n"
-                   "gfx950 c64 256 16,16 0.02\n")
+    key = fftc.tune_key()
+    src.write_text(f"{key} c64 1024 pease:4,4,4,4,4 0.05\n"
+                   f"{key} c64 256 foo:2,2,2,2,2,2,2,2 0.1\n"      # unknown order
+                   f"{key} c64 4096 ct:4,4 0.1\n"                  # does not multiply to n
+                   f"{key} c64 512 ct:2,2,2,2,2,2,2,2,2 0.1\n"     # not compiled
+                   f"{key} c128 64 ct:8,8 0.01\n"
+                   f"{key} c128 4096 fourstep:16,16,16 0.03\n"
+                   f"{key} c64 256 16,16 0.02\n")
     try:
         assert fftc.tune_load(str(src)) == 4
         out = tmp_path / "out.txt"

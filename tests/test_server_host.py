@@ -124,3 +124,72 @@ def test_calls_without_server():
         srv.stats()
     assert e.value.status == 6
     assert srv.submit(64, 1, fftc.FORWARD, FAKE_IN, 0) == 6
+
+
+def test_injected_arena_fault_fails_one_request_and_serving_continues(mock_server):
+    """fftc_fault_set(k): the k-th arena allocation fails that request with
+    FFTC_ERR_OUT_OF_MEMORY; nothing leaks and later requests are served."""
+    mock_server(8 << 20, max_inflight=2)
+    srv.fault_set(3)
+    try:
+        for tag in range(6):
+            assert srv.submit(256, 4, fftc.FORWARD, FAKE_IN, tag) == 0
+        got = _drain(6)
+        assert len(got) == 6
+        assert sorted(c["status"] for c in got) == [0, 0, 0, 0, 0, 3]
+        failed = [c for c in got if c["status"] == 3][0]
+        assert failed["tag"] == 2 and failed["out"] == 0        # admission order: the third request
+        st = srv.stats()
+        assert st["failed"] == 1 and st["completed"] == 6 and st["bytes_in_use"] == 0
+        assert srv.fault_count() >= 6
+        for tag in range(6, 12):
+            assert srv.submit(1024, 2, fftc.INVERSE, FAKE_IN, tag) == 0
+        got = _drain(6)
+        assert len(got) == 6 and all(c["status"] == 0 for c in got)
+        assert srv.stats()["bytes_in_use"] == 0
+    finally:
+        srv.fault_set(0)
+
+
+def test_fault_and_log_environment_in_a_fresh_process(tmp_path):
+    """FFTC_FAULT=2 and FFTC_LOG=1 set in the environment of a new process."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys, time; sys.path.insert(0, %r)\n"
+        "from paper_2207_06803_amd import fftc, server as srv\n"
+        "srv.start(1 << 20, n_streams=1, max_inflight=1, executor=srv.EXECUTOR_MOCK, mock_ns_per_mb=1000)\n"
+        "for t in range(3): assert srv.submit(64, 2, fftc.FORWARD, 0x10000, t) == 0\n"
+        "got = []\n"
+        "t0 = time.time()\n"
+        "while len(got) < 3 and time.time() - t0 < 20:\n"
+        "    for c in srv.poll():\n"
+        "        got.append(c)\n"
+        "        if c['status'] == 0: srv.release(c['out'])\n"
+        "srv.stop(drain=True)\n"
+        "print(sorted((c['tag'], c['status']) for c in got))\n" % root)
+    env = dict(os.environ, FFTC_FAULT="2", FFTC_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "[(0, 0), (1, 3), (2, 0)]"
+    assert "fftc: server start" in r.stderr and "fftc: injected allocation failure" in r.stderr
+    assert "fftc: server stop" in r.stderr
+
+
+def test_server_config_tune_db(tmp_path):
+    """fftc_server_config.tune_db is merged into the tuning database at start;
+    an unreadable file fails the start."""
+    fftc.tune_clear()
+    db = tmp_path / "tune.txt"
+    db.write_text(f"{fftc.tune_key()} c64 1024 16,4,16 0.010\n")
+    try:
+        srv.start(1 << 20, executor=srv.EXECUTOR_MOCK, tune_db=str(db))
+        srv.stop(drain=True)
+        assert fftc.factorize(1024)[0] == [16, 4, 16]
+        with pytest.raises(fftc.FFTCError) as e:
+            srv.start(1 << 20, executor=srv.EXECUTOR_MOCK, tune_db=str(tmp_path / "missing.txt"))
+        assert e.value.status == 1
+    finally:
+        fftc.tune_clear()

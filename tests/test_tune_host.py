@@ -14,11 +14,17 @@ def clean_db():
 def test_loaded_entry_drives_the_planner(tmp_path):
     default, _ = fftc.factorize(1024)
     db = tmp_path / "tune.txt"
-    db.write_text("gfx950 c64 1024 16,4,16 0.010\n"
-                  "gfx950 c64 512 3,3,3 0.1\n"        # does not multiply to 512: ignored
-                  "gfx942 c64 2048 16,16,8 0.1\n"     # other architecture: ignored
-                  "gfx950 c64 256 6,6 0.1\n"          # radix 6 unsupported: ignored
-                  "gfx950 c128 64 4,16 0.001\n")
+    key = fftc.tune_key()
+    arch, toolchain = key.split()
+    assert arch == "gfx950" and toolchain.startswith("hip")
+    db.write_text(f"{key} c64 1024 16,4,16 0.010\n"
+                  f"{key} c64 512 3,3,3 0.1\n"            # does not multiply to 512: ignored
+                  f"gfx942 {toolchain} c64 2048 16,16,8 0.1\n"  # other architecture: ignored
+                  f"{arch} hip0.0.0 c64 2048 16,16,8 0.1\n"     # other toolchain: ignored
+                  "gfx950 c64 2048 16,16,8 0.1\n"        # old format without the toolchain: ignored
+                  f"{key} c64 256 6,6 0.1\n"              # radix 6 unsupported: ignored
+                  f"{key} c64 64 4,16 0.1 extra\n"        # trailing field: ignored
+                  f"{key} c128 64 4,16 0.001\n")
     assert fftc.tune_load(str(db)) == 2
     assert fftc.factorize(1024)[0] == [16, 4, 16]
     assert fftc.factorize(64, "c128")[0] == [4, 16]
@@ -26,7 +32,7 @@ def test_loaded_entry_drives_the_planner(tmp_path):
     out = tmp_path / "saved.txt"
     assert fftc.tune_save(str(out)) == 2
     lines = sorted(out.read_text().split("\n"))
-    assert any(l.startswith("gfx950 c64 1024 16,4,16 ") for l in lines)
+    assert any(l.startswith(f"{key} c64 1024 16,4,16 ") for l in lines)
     fftc.tune_clear()
     assert fftc.factorize(1024)[0] == default
     assert fftc.tune_load(str(out)) == 2
