@@ -412,7 +412,10 @@ const char *fftc_tune_key(void);
  * allocation from then on fail with FFTC_ERR_OUT_OF_MEMORY before any HIP
  * call (a failed arena allocation fails that request only; the server keeps
  * serving), FFTC_LOG=1 logs plans, server start/stop and injected faults to
- * stderr.  fftc_fault_set(k) sets the same counter from code (k <= 0: off).
+ * stderr, FFTC_ROCTX=1 adds roctx ranges (fftc_plan, fftc_execute,
+ * fftc_execute_batch, fftc_server_round) for rocprofv3 --marker-trace,
+ * loading the ROCm profiler's roctx library at run time.  fftc_fault_set(k)
+ * sets the fault counter from code (k <= 0: off).
  * ------------------------------------------------------------------------- */
 fftc_status fftc_fault_set(int64_t k);
 /* Allocations counted since the last fftc_fault_set (or FFTC_FAULT). */

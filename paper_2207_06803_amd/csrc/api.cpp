@@ -1,4 +1,5 @@
 // C ABI: plans, execution, errors.  No exception crosses this boundary.
+#include <dlfcn.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -35,11 +36,38 @@ static std::once_flag g_env_once;
 static std::atomic<int64_t> g_fault_at{0}, g_alloc_count{0};
 static std::atomic<bool> g_log{false};
 
+using RangePushFn = int (*)(const char*);
+using RangePopFn = int (*)();
+static RangePushFn g_range_push = nullptr;
+static RangePopFn g_range_pop = nullptr;
+
 static void read_env() {
     std::call_once(g_env_once, [] {
         if (const char* f = getenv("FFTC_FAULT")) g_fault_at = atoll(f);
         if (const char* l = getenv("FFTC_LOG")) g_log = *l && strcmp(l, "0") != 0;
+        const char* r = getenv("FFTC_ROCTX");
+        if (r && *r && strcmp(r, "0") != 0) {
+            void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+            if (!h) h = dlopen("librocprofiler-sdk-roctx.so", RTLD_NOW | RTLD_GLOBAL);
+            if (h) {
+                auto push = reinterpret_cast<RangePushFn>(dlsym(h, "roctxRangePushA"));
+                auto pop = reinterpret_cast<RangePopFn>(dlsym(h, "roctxRangePop"));
+                if (push && pop) {
+                    g_range_push = push;
+                    g_range_pop = pop;
+                }
+            }
+        }
     });
+}
+
+void range_push(const char* name) {
+    read_env();
+    if (g_range_push) g_range_push(name);
+}
+
+void range_pop() {
+    if (g_range_pop) g_range_pop();
 }
 
 bool log_on() {
@@ -375,6 +403,7 @@ fftc_status fftc_fault_set(int64_t k) {
 int64_t fftc_fault_count(void) { return g_alloc_count.load(); }
 
 fftc_status fftc_plan(int64_t n, int64_t batch, int direction, int dtype, fftc_plan_t* plan_out) {
+    Range r("fftc_plan");
     try {
         return plan_impl(n, batch, direction, dtype, nullptr, 0, plan_out);
     } catch (...) {
@@ -459,10 +488,12 @@ static fftc_status execute_impl(fftc_plan_t p, const void* in, void* out, int64_
 }
 
 fftc_status fftc_execute(fftc_plan_t p, const void* in, void* out, void* stream) {
+    Range r("fftc_execute");
     return execute_impl(p, in, out, p ? p->batch : 0, stream);
 }
 
 fftc_status fftc_execute_batch(fftc_plan_t p, const void* in, void* out, int64_t batch, void* stream) {
+    Range r("fftc_execute_batch");
     return execute_impl(p, in, out, batch, stream);
 }
 

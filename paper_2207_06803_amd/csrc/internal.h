@@ -30,6 +30,15 @@ fftc_status dev_malloc(void** p, size_t bytes, const char* what);
 // and injected fault on stderr.
 bool log_on();
 void log_line(const char* fmt, ...);
+// FFTC_ROCTX=1 in the environment: roctx ranges (rocprofv3 --marker-trace)
+// around plan creation, execution and the server's launch rounds, through
+// the ROCm profiler's roctx library loaded at run time (no link dependency).
+void range_push(const char* name);
+void range_pop();
+struct Range {
+    explicit Range(const char* name) { range_push(name); }
+    ~Range() { range_pop(); }
+};
 
 #define FFTC_HIP_TRY(call)                                   \
     do {                                                     \

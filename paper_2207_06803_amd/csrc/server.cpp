@@ -385,6 +385,8 @@ class Server {
     }
 
     void launch_round(std::vector<std::pair<InFlight, int>>& to_launch) {
+        if (to_launch.empty()) return;
+        Range range("fftc_server_round");
         if (!cfg_.fuse || mock_ || to_launch.size() < 2) {
             for (auto& fl : to_launch) fl.first.status = launch(fl.first, fl.second);
             return;
