@@ -35,6 +35,29 @@ fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C*
         if (PASS == 1 && INV) v = cconj(v);
         buf[i] = v;
     }
+    // pass 1: the twiddles of the elements this thread stores, fetched with
+    // the data so their latency is spent before the stages, not after
+    // (w_N^{(col0 + c) p} = w_N^{col0 p} w_N^{c p}: the first from the fine and
+    // coarse tables once per p a thread stores, the second from the table
+    // twc[c M + p] = w_N^{c p} (c < TC) that follows them, read with
+    // consecutive lanes on consecutive p)
+    constexpr bool REPEAT = NTH % LEN == 0 || LEN % NTH == 0;
+    constexpr int PP = !REPEAT ? 1 : NTH % LEN == 0 ? 1 : LEN / NTH;  // distinct p per thread
+    constexpr int WIT = (PASS == 1 && REPEAT) ? IT : 1;
+    C wc[WIT], a[PP];
+    if constexpr (PASS == 1 && REPEAT) {
+        const C* twc = twn + kTwSplit + (int)((n + kTwSplit - 1) / kTwSplit);
+#pragma unroll
+        for (int pp = 0; pp < PP; ++pp) {
+            const int e = col0 * ((tid % LEN) + pp * NTH);  // < N <= 2^20
+            a[pp] = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
+        }
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int l = min(tid + i * NTH, TOT - 1);
+            wc[i] = twc[(l / LEN) * LEN + l % LEN];
+        }
+    }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
         const int l = tid + i * NTH;
@@ -45,24 +68,9 @@ fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C*
     spec_stages<K, 1, 0, true, false, false, Rs...>((const C*)nullptr, (C*)nullptr, lds + tr * LDSN, tw, t, true,
                                                      true);
     if constexpr (PASS == 1) {
-        // row-major store of column i = col0 + c: z[i M + p] w_N^{i p} (i p < N).
-        // w_N^{i p} = w_N^{col0 p} w_N^{c p}: the first from the fine and coarse
-        // tables once per p a thread stores, the second from the table
-        // twc[c M + p] = w_N^{c p} (c < TC) that follows them, read with
-        // consecutive lanes on consecutive p.
-        // (Lengths whose rows do not repeat per thread read both tables per
-        // element.)
-        constexpr bool REPEAT = NTH % LEN == 0 || LEN % NTH == 0;
-        constexpr int PP = !REPEAT ? 1 : NTH % LEN == 0 ? 1 : LEN / NTH;  // distinct p per thread
-        const C* twc = twn + kTwSplit + (int)((n + kTwSplit - 1) / kTwSplit);
-        C a[PP];
-        if constexpr (REPEAT) {
-#pragma unroll
-            for (int pp = 0; pp < PP; ++pp) {
-                const int e = col0 * ((tid % LEN) + pp * NTH);  // < N <= 2^20
-                a[pp] = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
-            }
-        }
+        // row-major store of column i = col0 + c: z[i M + p] w_N^{i p} (i p < N)
+        // (lengths whose rows do not repeat per thread read both tables per
+        // element)
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int l = tid + i * NTH;
@@ -70,7 +78,7 @@ fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C*
             if (l < TOT && c < cols) {
                 C w;
                 if constexpr (REPEAT) {
-                    w = cmul(a[i % PP], twc[c * LEN + p]);
+                    w = cmul(a[i % PP], wc[i]);
                 } else {
                     const int e = (col0 + c) * p;
                     w = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
