@@ -562,7 +562,23 @@ def layouts(torch, fftc, synth, timer):
 
 
 def orders(torch, fftc, synth, timer):
-    """Stockham against the alternative orders at 2^24 complex64 elements."""
+    """Stockham against the alternative orders at 2^24 complex64 elements, and
+    the order autotuner's pick (the tuning database is set aside before and
+    restored after, so its picks do not reach later workloads)."""
+    import tempfile
+    fd, saved = tempfile.mkstemp(suffix=".tune")
+    os.close(fd)
+    fftc.tune_save(saved)
+    fftc.tune_clear()
+    try:
+        return _orders(torch, fftc, synth, timer)
+    finally:
+        fftc.tune_clear()
+        fftc.tune_load(saved)
+        os.unlink(saved)
+
+
+def _orders(torch, fftc, synth, timer):
     x0 = torch.from_numpy(synth.uniform_complex(synth.rng(8), (ELEMS,), np.complex64)).to("cuda")
     xs = [x0.clone() for _ in range(NBUF)]  # rotating, as for the headline
     ys = [torch.empty_like(x0) for _ in range(NBUF)]
@@ -580,7 +596,7 @@ def orders(torch, fftc, synth, timer):
             with fftc.plan_order(n, b, fftc.FORWARD, "c64", order, radix) as p:
                 row[f"{fftc.ORDER_NAMES[order]}_r{radix}"] = timer.avg_ms(
                     lambda i: p.execute(xs[i % NBUF], ys[i % NBUF], timer.s), 10) * 1e3
-        res, best = fftc.autotune_orders(n, b, "c64", reps=5)
+        res, best = fftc.autotune_orders(n, b, "c64", reps=20)
         out[str(n)] = {"us": row, "hbm_gbs": {k: 16.0 * ELEMS / (v * 1e-6) / 1e9 for k, v in row.items()},
                        "autotuner_pick": f"{res[best][0]}_r{res[best][1]}" if res[best][1] else res[best][0]}
     del xs, ys

@@ -354,13 +354,19 @@ fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int *ra
  *                     in-place radix-R stages (decimation in time);
  *   FFTC_ORDER_PEASE  constant geometry: every stage reads x[j + r N/R] and
  *                     writes y[j R + r]; explicit digit reversal on output;
+ *   FFTC_ORDER_WAVE   N = 256 only (radix 16): Stockham with the stride
+ *                     permutation between its two radix-16 stages done inside
+ *                     the wave -- a 16 x 16 transpose across the 16 lanes of a
+ *                     transform by DPP quad permutes and ds_swizzle, no LDS
+ *                     and no barrier (the wavefront-shuffle exchange);
  *   FFTC_ORDER_FOURSTEP  Eq. 2 applied once (the block form): N = K M with
  *                     M = R^ceil(t/2), K = R^floor(t/2); Pi^N_K on load, DFT_M
  *                     on the K rows, D^N_M, DFT_K on the M columns (radix-R
  *                     Stockham stages for both), natural-order store.
  * Same conventions and results as fftc_plan (up to rounding).
  * ------------------------------------------------------------------------- */
-enum { FFTC_ORDER_STOCKHAM = 0, FFTC_ORDER_CT = 1, FFTC_ORDER_PEASE = 2, FFTC_ORDER_FOURSTEP = 3 };
+enum { FFTC_ORDER_STOCKHAM = 0, FFTC_ORDER_CT = 1, FFTC_ORDER_PEASE = 2, FFTC_ORDER_FOURSTEP = 3,
+       FFTC_ORDER_WAVE = 4 };
 
 fftc_status fftc_plan_order(int64_t n, int64_t batch, int direction, int dtype, int order, int radix,
                             fftc_plan_t *plan_out);

@@ -581,8 +581,10 @@ fftc_status fftc_plan_order(int64_t n, int64_t batch, int direction, int dtype, 
         if (dtype != FFTC_C64 && dtype != FFTC_C128)
             return fail(FFTC_ERR_INVALID_ARG, "order plans take FFTC_C64 or FFTC_C128");
         if (batch < 1 || batch > (int64_t(1) << 31)) return fail(FFTC_ERR_INVALID_ARG, "batch must be in [1, 2^31]");
-        if (order != FFTC_ORDER_CT && order != FFTC_ORDER_PEASE && order != FFTC_ORDER_FOURSTEP)
-            return fail(FFTC_ERR_INVALID_ARG, "order must be FFTC_ORDER_CT, FFTC_ORDER_PEASE or FFTC_ORDER_FOURSTEP");
+        if (order != FFTC_ORDER_CT && order != FFTC_ORDER_PEASE && order != FFTC_ORDER_FOURSTEP &&
+            order != FFTC_ORDER_WAVE)
+            return fail(FFTC_ERR_INVALID_ARG,
+                        "order must be FFTC_ORDER_CT, FFTC_ORDER_PEASE, FFTC_ORDER_FOURSTEP or FFTC_ORDER_WAVE");
         const OrderEntry* o = find_order(dtype, n, order, radix);
         if (!o)
             return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no compiled kernel for n = " + std::to_string(n) + ", radix " +

@@ -19,6 +19,15 @@
 //    digit-reversed order, and the explicit reversal is the store's read
 //    address.  (Derived from the Stockham stages by conjugating each with the
 //    digit permutation that makes its addressing constant.)
+//  ORDER_WAVE (Stockham, N = 256 = 16 x 16, the exchange between the two
+//    radix-16 stages inside the wave): each of 16 lanes loads one butterfly
+//    of the first stage straight from HBM and keeps its 16 outputs (row j of
+//    the 16 x 16 intermediate); the stride permutation L^256_16 is then the
+//    transpose of that 16 x 16 array across the 16 lanes, done as an xor
+//    butterfly over lane bits 1, 2, 4, 8 (at step m a lane swaps half of its
+//    registers with lane ^ m: DPP quad permutes for m = 1, 2, ds_swizzle for
+//    m = 4, 8) with no LDS and no barrier; the second stage's twiddles and
+//    butterflies follow, stored straight to HBM in natural order.
 //  ORDER_FOURSTEP (Eq. 2 applied once, the block form): N = K M with
 //    M = R^ceil(t/2), K = R^floor(t/2).  The load applies Pi^N_K (element
 //    x[j K + i] goes to row i, column j of a K x M array); the K rows are
@@ -35,7 +44,7 @@
 
 namespace fftc {
 
-enum { ORDER_STOCKHAM = 0, ORDER_CT = 1, ORDER_PEASE = 2, ORDER_FOURSTEP = 3 };
+enum { ORDER_STOCKHAM = 0, ORDER_CT = 1, ORDER_PEASE = 2, ORDER_FOURSTEP = 3, ORDER_WAVE = 4 };
 
 constexpr int ilog(int n, int r) { return n <= 1 ? 0 : 1 + ilog(n / r, r); }
 constexpr int ipow(int r, int e) { return e == 0 ? 1 : r * ipow(r, e - 1); }
@@ -201,6 +210,64 @@ order_kernel(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __restrict
     }
 }
 
+// Exchange of one 32-bit word with lane ^ M (M < 16, within a row of 16):
+// DPP quad permutes for M = 1, 2, ds_swizzle's bit mode (xor mask) for 4, 8.
+template <int M> __device__ __forceinline__ int xor_lane(int v) {
+    if constexpr (M == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);       // quad_perm 1,0,3,2
+    else if constexpr (M == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm 2,3,0,1
+    else return __builtin_amdgcn_ds_swizzle(v, (M << 10) | 0x1F);
+}
+template <int M> __device__ __forceinline__ float xor_lane_val(float v) { return __int_as_float(xor_lane<M>(__float_as_int(v))); }
+template <int M> __device__ __forceinline__ double xor_lane_val(double v) {
+    const int lo = xor_lane<M>(__double2loint(v)), hi = xor_lane<M>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// One step of the 16 x 16 transpose across 16 lanes: for each register pair
+// (j, j + M), j without bit M, the lane with bit M of its lane index set
+// sends register j and receives into it; the other sends j + M and receives
+// into j + M.  After steps M = 1, 2, 4, 8, register j of lane t holds what
+// register t of lane j held.
+template <int M, typename C> __device__ __forceinline__ void transpose_step(C* v, int t) {
+    const bool hi = (t & M) != 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j & M) continue;
+        const C a = v[j], b = v[j | M];
+        const C send = mk(hi ? a.x : b.x, hi ? a.y : b.y);
+        const C recv = mk(xor_lane_val<M>(send.x), xor_lane_val<M>(send.y));
+        v[j] = mk(hi ? recv.x : a.x, hi ? recv.y : a.y);
+        v[j | M] = mk(hi ? b.x : recv.x, hi ? b.y : recv.y);
+    }
+}
+
+template <typename Real, bool INV>
+__global__ void __launch_bounds__(256)
+wave_order_kernel(const cplx<Real>* in, cplx<Real>* out, const cplx<Real>* __restrict__ twn, int64_t batch) {
+    using C = cplx<Real>;
+    constexpr int N = 256, T = 16;
+    const int tid = (int)threadIdx.x, t = tid & 15;
+    const int64_t b0 = (int64_t)blockIdx.x * T;
+    const int q = tid >> 4;
+    const bool valid = b0 + q < batch;
+    const int64_t off = (valid ? b0 + q : batch - 1) * N;  // past the end: a real transform, not stored
+    C v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = ld_in<INV>(in + off + t + 16 * r);
+    Codelet<16, C>::run(v);  // lane t: element 16 t + r of the intermediate
+    transpose_step<1>(v, t);
+    transpose_step<2>(v, t);
+    transpose_step<4>(v, t);
+    transpose_step<8>(v, t);  // lane t: element t + 16 r, r = 0..15
+#pragma unroll
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twn[r * t]);  // w_256^{r t}
+    Codelet<16, C>::run(v);
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) st_out<INV>(out + off + t + 16 * r, v[r]);
+    }
+}
+
 template <typename Real, int N, int R, int ORDER>
 struct OrderInst {
     static constexpr int BPT0 = kMaxElemsPerThread / R >= 1 ? kMaxElemsPerThread / R : 1;
@@ -215,6 +282,18 @@ struct OrderInst {
         OrderEntry e{dtype, N, ORDER, R, TPT, T,
                      reinterpret_cast<const void*>(&order_kernel<Real, N, R, TPT, T, false, ORDER>),
                      reinterpret_cast<const void*>(&order_kernel<Real, N, R, TPT, T, true, ORDER>)};
+        return e;
+    }
+};
+
+// The in-wave exchange: N = 256, radix 16, 16 lanes per transform, 16
+// transforms per 256-thread workgroup.
+template <typename Real>
+struct WaveOrderInst {
+    static OrderEntry entry(int dtype) {
+        OrderEntry e{dtype, 256, ORDER_WAVE, 16, 16, 16,
+                     reinterpret_cast<const void*>(&wave_order_kernel<Real, false>),
+                     reinterpret_cast<const void*>(&wave_order_kernel<Real, true>)};
         return e;
     }
 };

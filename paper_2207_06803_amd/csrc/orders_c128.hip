@@ -1,6 +1,6 @@
 // c128 kernels of the alternative orders (orders.h): recursive Cooley-Tukey
-// with the explicit digit reversal, Pease's constant geometry, and the
-// four-step (block) form of Eq. 2.
+// with the explicit digit reversal, Pease's constant geometry, the
+// four-step (block) form of Eq. 2, and the in-wave exchange for N = 256.
 #include "internal.h"
 #include "orders.h"
 
@@ -11,7 +11,7 @@ namespace fftc {
 #define E(N, R)                                                              \
     OrderInst<double, N, R, ORDER_CT>::entry(FFTC_C128), OrderInst<double, N, R, ORDER_PEASE>::entry(FFTC_C128), \
         OrderInst<double, N, R, ORDER_FOURSTEP>::entry(FFTC_C128),
-static const OrderEntry k_table[] = {ORDER_LIST(E)};
+static const OrderEntry k_table[] = {ORDER_LIST(E) WaveOrderInst<double>::entry(FFTC_C128)};
 #undef E
 
 const OrderEntry* order_table_c128(int* count) {

@@ -1,6 +1,6 @@
 // c64 kernels of the alternative orders (orders.h): recursive Cooley-Tukey
-// with the explicit digit reversal, Pease's constant geometry, and the
-// four-step (block) form of Eq. 2.
+// with the explicit digit reversal, Pease's constant geometry, the
+// four-step (block) form of Eq. 2, and the in-wave exchange for N = 256.
 #include "internal.h"
 #include "orders.h"
 
@@ -11,7 +11,7 @@ namespace fftc {
 #define E(N, R)                                                              \
     OrderInst<float, N, R, ORDER_CT>::entry(FFTC_C64), OrderInst<float, N, R, ORDER_PEASE>::entry(FFTC_C64), \
         OrderInst<float, N, R, ORDER_FOURSTEP>::entry(FFTC_C64),
-static const OrderEntry k_table[] = {ORDER_LIST(E)};
+static const OrderEntry k_table[] = {ORDER_LIST(E) WaveOrderInst<float>::entry(FFTC_C64)};
 #undef E
 
 const OrderEntry* order_table_c64(int* count) {

@@ -137,8 +137,8 @@ std::vector<int> choose_radices(int64_t n, int dtype) {
 //   <arch> <toolchain> <c64|c128> <n> [<order>:]<r1,r2,...> <ms>
 // with <toolchain> the HIP version the library's kernels were compiled with
 // ("hip7.2.53211"): timings hold for one device and one compiler's code.
-// <order> is "ct", "pease" or "fourstep" for an alternative order (its list is
-// the radix repeated), none for Stockham.  Lines for another architecture or
+// <order> is "ct", "pease", "fourstep" or "wave" for an alternative order (its
+// list is the radix repeated), none for Stockham.  Lines for another architecture or
 // toolchain, lines in another format, and lists that do not multiply to n are
 // ignored.
 namespace {
@@ -172,7 +172,11 @@ int load_locked(const char* path) {
         char* list = rl;
         if (char* colon = strchr(rl, ':')) {
             *colon = 0;
-            order = strcmp(rl, "ct") == 0 ? 1 : strcmp(rl, "pease") == 0 ? 2 : strcmp(rl, "fourstep") == 0 ? 3 : -1;
+            order = strcmp(rl, "ct") == 0         ? 1
+                    : strcmp(rl, "pease") == 0    ? 2
+                    : strcmp(rl, "fourstep") == 0 ? 3
+                    : strcmp(rl, "wave") == 0     ? 4
+                                                  : -1;
             list = colon + 1;
         }
         if (order < 0) continue;
@@ -254,7 +258,10 @@ int tune_save_file(const char* path) {
         fprintf(f, "%s %s %s %lld ", kTuneArch, kTuneToolchain, kv.first.second == FFTC_C128 ? "c128" : "c64",
                 (long long)kv.first.first);
         if (kv.second.order)
-            fprintf(f, "%s:", kv.second.order == 1 ? "ct" : kv.second.order == 2 ? "pease" : "fourstep");
+            fprintf(f, "%s:", kv.second.order == 1   ? "ct"
+                              : kv.second.order == 2 ? "pease"
+                              : kv.second.order == 3 ? "fourstep"
+                                                     : "wave");
         const auto& rs = kv.second.rs;
         for (size_t i = 0; i < rs.size(); ++i) fprintf(f, i ? ",%d" : "%d", rs[i]);
         fprintf(f, " %.6f\n", kv.second.ms);

@@ -36,7 +36,8 @@ ORDER_STOCKHAM = 0
 ORDER_CT = 1
 ORDER_PEASE = 2
 ORDER_FOURSTEP = 3
-ORDER_NAMES = {0: "stockham", 1: "ct", 2: "pease", 3: "fourstep"}
+ORDER_WAVE = 4
+ORDER_NAMES = {0: "stockham", 1: "ct", 2: "pease", 3: "fourstep", 4: "wave"}
 
 # formula plan flags
 FORMULA_NO_FOLD = 1
@@ -405,7 +406,8 @@ def execute_layout(plan: Plan, in_re, in_im, out_re, out_im, stream=None) -> Non
 
 
 def plan_order(n: int, batch: int, direction: int = FORWARD, dtype="c64", order=ORDER_CT, radix: int = 2) -> Plan:
-    """Plan running an alternative factorisation order (ORDER_CT / ORDER_PEASE / ORDER_FOURSTEP)."""
+    """Plan running an alternative factorisation order (ORDER_CT / ORDER_PEASE / ORDER_FOURSTEP /
+    ORDER_WAVE)."""
     h = _vp()
     check(lib.fftc_plan_order(n, batch, direction, dtype_code(dtype), int(order), int(radix), ctypes.byref(h)),
           "fftc_plan_order")

@@ -14,6 +14,7 @@ def test_compiled_orders():
         want = {(n, o, r) for n, r in [(64, 2), (64, 4), (64, 8), (256, 2), (256, 4), (256, 16), (1024, 2),
                                         (1024, 4), (4096, 2), (4096, 4), (4096, 8), (4096, 16)]
                 for o in (fftc.ORDER_CT, fftc.ORDER_PEASE, fftc.ORDER_FOURSTEP)}
+        want.add((256, fftc.ORDER_WAVE, 16))       # the in-wave exchange: N = 256 only
         assert set(got) == want
         for n, _, r in got:
             m = n
@@ -31,7 +32,8 @@ def _plan_status(n, order, radix, dtype="c64", batch=1, direction=fftc.FORWARD):
 
 def test_plan_order_errors():
     assert _plan_status(1024, 0, 2) == 1          # Stockham goes through fftc_plan
-    assert _plan_status(1024, 4, 2) == 1          # no such order
+    assert _plan_status(1024, 7, 2) == 1          # no such order
+    assert _plan_status(1024, fftc.ORDER_WAVE, 16) == 2  # the in-wave exchange is compiled for N = 256 only
     assert _plan_status(1024, fftc.ORDER_CT, 16) == 2   # 1024 is not a power of 16
     assert _plan_status(2048, fftc.ORDER_PEASE, 2) == 2  # not compiled
     assert _plan_status(1024, fftc.ORDER_CT, 2, dtype="split_f16") == 1
