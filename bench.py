@@ -70,12 +70,14 @@ def parse():
                     help="only run plain 128 MiB device copies (counter calibration)")
     ap.add_argument("--rocpd-summary", nargs="+", metavar="DB",
                     help="print per-kernel durations and counters from rocprofv3 databases, then exit")
-    ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+    ap.add_argument("--traffic-json", nargs="+", metavar="DB",
                     help="write profiles/hbm_traffic.json from FETCH_SIZE / WRITE_SIZE runs of the headline "
-                         "and of --calibrate-copy, then exit")
+                         "and of --calibrate-copy (FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB), and "
+                         "optionally a run of the headline with the read requests counted by size "
+                         "(TCC_EA0_RDREQ, _32B, _64B, _128B) that pins the FETCH_SIZE scale, then exit")
     ap.add_argument("--profile-set", default="",
                     help="only launch the named hot-path kernels a few times each, for counter runs: comma-separated "
-                         "from mixed, split, two_pass, c64_16384, copy")
+                         "from mixed, split, two_pass, c64_16384, wave256, copy")
     ap.add_argument("--extras", default="",
                     help="comma-separated names of the extra workloads to run (default: all)")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -611,9 +613,13 @@ def config5(args, torch, fftc, synth, fuse=True, rate=None, nreq=None):
     nreq = nreq or args.serve_requests
     g = synth.rng(5)
     reqs = synth.serving_requests(synth.rng(5, 99), nreq, rate)
-    pool_elems = (1 << 24) + (1 << 20)
-    pool = torch.from_numpy(synth.uniform_complex(g, (pool_elems,), np.complex64)).to("cuda")
-    offs = g.integers(0, (1 << 20), size=nreq)
+    # inputs come from a 1.125 GiB device pool (past the 256 MB last-level
+    # cache): a seeded 2^24-element block and scaled copies of it; request i
+    # reads from a random element offset below 2^27
+    block = torch.from_numpy(synth.uniform_complex(g, (1 << 24,), np.complex64)).to("cuda")
+    pool = torch.cat([block * (1.0 + 0.0625 * k) for k in range(9)])
+    del block
+    offs = g.integers(0, (1 << 27), size=nreq)
     budget = 64 << 30
     srv.start(budget, n_streams=args.serve_streams, max_inflight=64, fuse=fuse)
     try:
@@ -682,7 +688,8 @@ def config5(args, torch, fftc, synth, fuse=True, rate=None, nreq=None):
             "queue_p99_us": float(np.percentile(q, 99)),
             "sustained_gflops": fl / span / 1e9, "sustained_hbm_gbs": by / span / 1e9,
             "span_s": span, "offered_gbs": by / (reqs["arrival_s"][-1] + 1e-9) / 1e9,
-            "peak_budget_bytes": st["peak_bytes"], "max_inflight_seen": st["max_inflight_seen"]}
+            "peak_budget_bytes": st["peak_bytes"], "max_inflight_seen": st["max_inflight_seen"],
+            "input_pool_bytes": int(pool.numel()) * 8, "plan_bytes": st["plan_bytes"]}
 
 
 def serving_sweep(args, torch, fftc, synth):
@@ -785,6 +792,15 @@ def profile_set(names, torch, fftc, synth):
             with fftc.Plan(n, ELEMS // n, fftc.FORWARD, "c64") as p:
                 launches(f"c64 N={n} batch {ELEMS // n} ({p.describe()['variant']})", [p], xs, ys, 3)
         del x, xs, ys
+    if "wave256" in names:
+        x = torch.from_numpy(synth.uniform_complex(synth.rng(8), (ELEMS,), np.complex64)).to("cuda")
+        xs = [x] + [x.clone() for _ in range(NBUF - 1)]
+        ys = [torch.empty_like(x) for _ in range(NBUF)]
+        with fftc.Plan(256, ELEMS // 256, fftc.FORWARD, "c64") as p:
+            launches("c64 N=256 Stockham (LDS exchange)", [p], xs, ys)
+        with fftc.plan_order(256, ELEMS // 256, fftc.FORWARD, "c64", fftc.ORDER_WAVE, 16) as p:
+            launches("c64 N=256 in-wave exchange", [p], xs, ys)
+        del x, xs, ys
     if "copy" in names:
         x = torch.zeros(ELEMS, dtype=torch.complex64, device="cuda")
         y = torch.empty_like(x)
@@ -833,12 +849,20 @@ def _counter_means(path, counter):
     return {k: sum(v) / len(v) for k, v in agg.items()}
 
 
-def traffic_json(fetch_db, write_db, copy_fetch_db, copy_write_db):
+def traffic_json(fetch_db, write_db, copy_fetch_db, copy_write_db, rdreq_db=None):
     """Calibrated HBM bytes per launch of the headline kernels: FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch) scaled by what they read for a plain copy of
-    2^24 complex64 (128 MiB read, 128 MiB written)."""
+    2^24 complex64 (128 MiB read, 128 MiB written).  With a run that counts
+    the read requests by size, each kernel's read bytes are also summed
+    directly (128 B x RDREQ_128B + 64 B x RDREQ_64B + 32 B x RDREQ_32B), which
+    pins the FETCH_SIZE scale without the copy."""
     import re
     cf, cw = _counter_means(copy_fetch_db, "FETCH_SIZE"), _counter_means(copy_write_db, "WRITE_SIZE")
+    by_size = {}
+    if rdreq_db:
+        for c, w in (("TCC_EA0_RDREQ_128B", 128), ("TCC_EA0_RDREQ_64B", 64), ("TCC_EA0_RDREQ_32B", 32)):
+            for k, v in _counter_means(rdreq_db, c).items():
+                by_size[k] = by_size.get(k, 0.0) + w * v
     copy_name = max(cf, key=cf.get)
     kib = 8.0 * ELEMS / 1024
     fscale, wscale = kib / cf[copy_name], kib / cw[copy_name]
@@ -853,6 +877,9 @@ def traffic_json(fetch_db, write_db, copy_fetch_db, copy_write_db):
         kernels[key] = {"kernel": name, "fetch_kib_raw": round(fetch[name], 1), "write_kib_raw": round(write[name], 1),
                         "bytes_per_launch": int(round(b)), "algorithmic_bytes": 16 * ELEMS,
                         "ratio_to_algorithmic": round(b / (16 * ELEMS), 5)}
+        if name in by_size:
+            kernels[key]["read_bytes_by_request_size"] = int(round(by_size[name]))
+            kernels[key]["fetch_scale_pinned"] = round(by_size[name] / 1024 / fetch[name], 5)
     out = {"source_hash": source_hash(),
            "sources": list(HEADLINE_SOURCES) + ["spec_list.inc (complex64 lists of N = %s)" % ", ".join(map(str, SIZES))],
            "calibration": {"kernel": f"{copy_name} (torch copy_ of 2^24 complex64)", "bytes_read": 8 * ELEMS,
@@ -873,6 +900,8 @@ def main():
         rocpd_summary(args.rocpd_summary)
         return
     if args.traffic_json:
+        if len(args.traffic_json) not in (4, 5):
+            sys.exit("--traffic-json takes 4 or 5 databases")
         traffic_json(*args.traffic_json)
         return
     if args.gpus != 1:
