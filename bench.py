@@ -70,6 +70,9 @@ def parse():
                     help="only run plain 128 MiB device copies (counter calibration)")
     ap.add_argument("--rocpd-summary", nargs="+", metavar="DB",
                     help="print per-kernel durations and counters from rocprofv3 databases, then exit")
+    ap.add_argument("--counter-report", nargs="+", metavar="DB",
+                    help="one markdown table of per-dispatch counters and derived rates per kernel and grid: the "
+                         "first database is a kernel trace, the rest counter runs of the same program, then exit")
     ap.add_argument("--traffic-json", nargs="+", metavar="DB",
                     help="write profiles/hbm_traffic.json from FETCH_SIZE / WRITE_SIZE runs of the headline "
                          "and of --calibrate-copy (FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB), and "
@@ -838,6 +841,83 @@ def rocpd_summary(paths):
         print()
 
 
+CU_COUNT, SIMDS_PER_CU, XCDS = 256, 4, 8
+
+
+def counter_report(trace_db, pmc_dbs):
+    """Counters of several single-pass rocprofv3 runs of one program, merged
+    per (kernel, grid size, workgroup size) with the kernel trace of the same
+    program, and the rates derived from them:
+      read bytes   128 RDREQ_128B + 64 RDREQ_64B + 32 RDREQ_32B (memory-side
+                   read requests counted by size, all channels);
+      write bytes  64 WRREQ_64B + 32 (WRREQ - WRREQ_64B);
+      HBM rate     (read + write bytes) / mean traced duration;
+      conflict     LDS bank-conflict cycles per LDS instruction;
+      LDS wait     share of wave cycles spent waiting on LDS instructions;
+      MFMA busy    matrix-core busy cycles / (GUI-active cycles of one XCD x
+                   SIMDs), the profiler's MfmaUtil (GRBM_GUI_ACTIVE is summed
+                   over the 8 XCDs here, so one XCD's count is the sum / 8);
+      occupancy    mean resident waves per CU (MeanOccupancyPerCU)."""
+    import re
+    import sqlite3
+
+    def key(name, grid, wg):
+        return (re.sub(r"[(].*", "", name), int(grid), int(wg))
+
+    trace = {}
+    db = sqlite3.connect(trace_db)
+    for name, gx, gy, gz, wx, wy, wz, dur, vgpr, agpr, lds, scr in db.execute(
+            "select name, grid_x, grid_y, grid_z, workgroup_x, workgroup_y, workgroup_z, duration, vgpr_count, "
+            "accum_vgpr_count, lds_size, scratch_size from kernels"):
+        t = trace.setdefault(key(name, gx * gy * gz, wx * wy * wz), {"durs": [], "regs": (vgpr, agpr, lds, scr)})
+        t["durs"].append(dur)
+    ctr = {}
+    for path in pmc_dbs:
+        db = sqlite3.connect(path)
+        for name, grid, wg, cn, val in db.execute(
+                "select kernel_name, grid_size, workgroup_size, counter_name, value from counters_collection"):
+            ctr.setdefault(key(name, grid, wg), {}).setdefault(cn, []).append(val)
+    rows = []
+    for k in sorted(set(trace) | set(ctr), key=lambda k: (k[0], k[1])):
+        name, grid, wg = k
+        if "elementwise" in name or "twiddle_kernel" in name:
+            continue
+        c = {cn: sum(v) / len(v) for cn, v in ctr.get(k, {}).items()}
+        t = trace.get(k)
+        us = sum(t["durs"]) / len(t["durs"]) / 1e3 if t else None
+
+        def g(*names):
+            return all(n in c for n in names)
+
+        rd = wr = None
+        if g("TCC_EA0_RDREQ_128B", "TCC_EA0_RDREQ_64B", "TCC_EA0_RDREQ_32B"):
+            rd = 128 * c["TCC_EA0_RDREQ_128B"] + 64 * c["TCC_EA0_RDREQ_64B"] + 32 * c["TCC_EA0_RDREQ_32B"]
+        if g("TCC_EA0_WRREQ", "TCC_EA0_WRREQ_64B"):
+            wr = 64 * c["TCC_EA0_WRREQ_64B"] + 32 * (c["TCC_EA0_WRREQ"] - c["TCC_EA0_WRREQ_64B"])
+        waves = c.get("SQ_WAVES")
+        f = lambda v, fmt: "-" if v is None else fmt % v
+        per_wave = lambda n: c[n] / waves if waves and n in c else None
+        rows.append("| `%s` | %d | %d | %s | %s | %s | %s | %s | %s | %s | %s | %s | %s | %s | %s | %s |" % (
+            name, grid, wg, f(len(t["durs"]) if t else None, "%d"), f(us, "%.2f"),
+            "-" if not t else "%d/%d/%d/%d" % t["regs"], f(waves, "%.0f"),
+            f(per_wave("SQ_INSTS_VALU"), "%.1f"), f(per_wave("SQ_INSTS_LDS"), "%.1f"),
+            f(per_wave("SQ_INSTS_MFMA"), "%.1f"),
+            f(c["SQ_LDS_BANK_CONFLICT"] / c["SQ_INSTS_LDS"] if g("SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS") and
+              c["SQ_INSTS_LDS"] else None, "%.2f"),
+            f(100 * c["SQ_WAIT_INST_LDS"] / c["SQ_WAVE_CYCLES"] if g("SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES") and
+              c["SQ_WAVE_CYCLES"] else None, "%.1f%%"),
+            f(100 * c["SQ_VALU_MFMA_BUSY_CYCLES"] / (c["GRBM_GUI_ACTIVE"] / XCDS * CU_COUNT * SIMDS_PER_CU)
+              if g("SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE") and c["GRBM_GUI_ACTIVE"] else None, "%.1f%%"),
+            f(c.get("MeanOccupancyPerCU"), "%.1f"),
+            "-" if rd is None or wr is None else "%.1f / %.1f" % (rd / 2**20, wr / 2**20),
+            f((rd + wr) / (us * 1e3) if rd is not None and wr is not None and us else None, "%.0f")))
+    print("| kernel | grid (threads) | workgroup | calls | mean us | VGPR/AGPR/LDS/scratch | waves | "
+          "VALU/wave | LDS/wave | MFMA/wave | conflict cyc/LDS inst | LDS wait | MFMA busy | occupancy | "
+          "read / write MiB | HBM GB/s |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|")
+    print("\n".join(rows))
+
+
 def _counter_means(path, counter):
     import re
     import sqlite3
@@ -847,6 +927,13 @@ def _counter_means(path, counter):
         if cn == counter:
             agg.setdefault(re.sub(r"[(].*", "", name), []).append(val)
     return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def headline_key(name):
+    """'c64_<N>_fwd|inv' for a complex64 Stockham kernel's name, else None."""
+    import re
+    m = re.match(r"void fftc::stockham_spec<fftc::SpecCfg<float, (\d+), \d+, \d+, (true|false)(?:, false)?>", name)
+    return m and f"c64_{m.group(1)}_{'inv' if m.group(2) == 'true' else 'fwd'}"
 
 
 def traffic_json(fetch_db, write_db, copy_fetch_db, copy_write_db, rdreq_db=None):
@@ -869,10 +956,9 @@ def traffic_json(fetch_db, write_db, copy_fetch_db, copy_write_db, rdreq_db=None
     fetch, write = _counter_means(fetch_db, "FETCH_SIZE"), _counter_means(write_db, "WRITE_SIZE")
     kernels = {}
     for name in fetch:
-        m = re.search(r"SpecCfg<float, (\d+), \d+, \d+, (true|false)>", name)
-        if not m or name not in write:
+        key = headline_key(name)
+        if not key or name not in write:
             continue
-        key = f"c64_{m.group(1)}_{'inv' if m.group(2) == 'true' else 'fwd'}"
         b = (fetch[name] * fscale + write[name] * wscale) * 1024
         kernels[key] = {"kernel": name, "fetch_kib_raw": round(fetch[name], 1), "write_kib_raw": round(write[name], 1),
                         "bytes_per_launch": int(round(b)), "algorithmic_bytes": 16 * ELEMS,
@@ -898,6 +984,11 @@ def main():
     args = parse()
     if args.rocpd_summary:
         rocpd_summary(args.rocpd_summary)
+        return
+    if args.counter_report:
+        if len(args.counter_report) < 2:
+            sys.exit("--counter-report takes a kernel trace and at least one counter run")
+        counter_report(args.counter_report[0], args.counter_report[1:])
         return
     if args.traffic_json:
         if len(args.traffic_json) not in (4, 5):
