@@ -11,6 +11,9 @@
 
 namespace fftc {
 
+constexpr int ilog2_ceil(int x) { return x <= 1 ? 0 : 1 + ilog2_ceil((x + 1) / 2); }
+static_assert(ilog2_ceil(16) == 4 && ilog2_ceil(17) == 5 && ilog2_ceil(2) == 1 && ilog2_ceil(1) == 0, "");
+
 template <class K, int PASS, bool INV, int... Rs>
 __global__ void __launch_bounds__(K::TPT * K::T)
 fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C* __restrict__ tw,
@@ -36,26 +39,31 @@ fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C*
         buf[i] = v;
     }
     // pass 1: the twiddles of the elements this thread stores, fetched with
-    // the data so their latency is spent before the stages, not after
-    // (w_N^{(col0 + c) p} = w_N^{col0 p} w_N^{c p}: the first from the fine and
-    // coarse tables once per p a thread stores, the second from the table
-    // twc[c M + p] = w_N^{c p} (c < TC) that follows them, read with
-    // consecutive lanes on consecutive p)
+    // the data so their latency is spent before the stages, not after.  A
+    // thread stores PP distinct rows p, and for each the columns
+    // c = c0 + s S, s < CN, of its tile, so
+    //   w_N^{(col0 + c) p} = w_N^{(col0 + c0) p} (w_N^{S p})^s:
+    // the first factor from the fine and coarse tables once per p, and the
+    // powers w_N^{2^b S p} (b < log2 CN) from the table twc[c M + p] = w_N^{c p}
+    // (c < TC) that follows them, read with consecutive lanes on consecutive
+    // p.  The other powers are products of these (at most log2 CN - 1 extra
+    // roundings), formed after the stages.
     constexpr bool REPEAT = NTH % LEN == 0 || LEN % NTH == 0;
     constexpr int PP = !REPEAT ? 1 : NTH % LEN == 0 ? 1 : LEN / NTH;  // distinct p per thread
-    constexpr int WIT = (PASS == 1 && REPEAT) ? IT : 1;
-    C wc[WIT], a[PP];
+    constexpr int S = !REPEAT ? 1 : NTH % LEN == 0 ? NTH / LEN : 1;   // column step between a p's stores
+    constexpr int CN = (IT + PP - 1) / PP;                             // stores per p
+    constexpr int NB = (PASS == 1 && REPEAT) ? ilog2_ceil(CN) : 0;     // loaded powers per p
+    C a[PP], pw[PP][NB > 0 ? NB : 1];
     if constexpr (PASS == 1 && REPEAT) {
         const C* twc = twn + kTwSplit + (int)((n + kTwSplit - 1) / kTwSplit);
+        const int c0 = NTH % LEN == 0 ? tid / LEN : 0;
 #pragma unroll
         for (int pp = 0; pp < PP; ++pp) {
-            const int e = col0 * ((tid % LEN) + pp * NTH);  // < N <= 2^20
+            const int p = (tid % LEN) + pp * NTH;
+            const int e = (col0 + c0) * p;  // < N <= 2^20
             a[pp] = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);
-        }
 #pragma unroll
-        for (int i = 0; i < IT; ++i) {
-            const int l = min(tid + i * NTH, TOT - 1);
-            wc[i] = twc[(l / LEN) * LEN + l % LEN];
+            for (int b = 0; b < NB; ++b) pw[pp][b] = twc[((S << b) % TC) * LEN + p];
         }
     }
 #pragma unroll
@@ -70,15 +78,26 @@ fourstep_spec(const typename K::C* src, typename K::C* dst, const typename K::C*
     if constexpr (PASS == 1) {
         // row-major store of column i = col0 + c: z[i M + p] w_N^{i p} (i p < N)
         // (lengths whose rows do not repeat per thread read both tables per
-        // element)
+        // element).  v[i] = w_N^{(col0 + c) p} of store i, built from an
+        // earlier store's factor of the same p times one loaded power.
+        C v[REPEAT ? IT : 1];
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int l = tid + i * NTH;
             const int c = l / LEN, p = l % LEN;
+            if constexpr (REPEAT) {
+                const int pp = i % PP, s = i / PP;
+                if (s == 0) {
+                    v[i] = a[pp];
+                } else {
+                    const int hb = 31 - __builtin_clz(s);  // compile-time after unrolling
+                    v[i] = cmul(v[i - (PP << hb)], pw[pp][hb]);
+                }
+            }
             if (l < TOT && c < cols) {
                 C w;
                 if constexpr (REPEAT) {
-                    w = cmul(a[i % PP], wc[i]);
+                    w = v[i];
                 } else {
                     const int e = (col0 + c) * p;
                     w = cmul(twn[e % kTwSplit], twn[kTwSplit + e / kTwSplit]);

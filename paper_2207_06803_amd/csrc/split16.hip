@@ -106,12 +106,15 @@ template <int N> constexpr int split_tail() {
     while (m % 16 == 0) m /= 16;
     return m;
 }
-// Waves per transform: one per group of 16 butterflies up to four (N = 256:
-// 1, 512: 2, 1024 .. 4096: 4), then one per 1024 elements (measured at batch
-// 8192: one wave for N = 1024 holding all four groups took 55 us against
-// 47 us with four).
+// Waves per transform: one per group of 16 butterflies for N = 256 and 512,
+// two for N = 1024 and 2048 (two and four groups each), four for 4096, then
+// one per 1024 elements.  Measured at batch 8192, N = 1024: two waves of two
+// groups took 32.2 us (fp16 split) and 39.2 us (bf16 three-term) against
+// 33.7 and 45.2 us with four waves of one group, and one wave of four groups
+// was slower still; N = 2048: 60.7 / 69.8 us against 61.9 / 72.9 us; N =
+// 4096: two waves were slower (125.9 / 211.6 us against 115.8 / 172.6 us).
 __host__ __device__ constexpr int split_waves_for(int64_t n) {
-    return n <= 4096 ? (n / 256 < 4 ? (n / 256 < 1 ? 1 : (int)(n / 256)) : 4) : (int)(n / 1024);
+    return (n == 1024 || n == 2048) ? 2 : n <= 4096 ? (n / 256 < 4 ? (n / 256 < 1 ? 1 : (int)(n / 256)) : 4) : (int)(n / 1024);
 }
 template <int N> constexpr int split_waves() { return split_waves_for(N); }
 
