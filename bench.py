@@ -782,7 +782,7 @@ def profile_set(names, torch, fftc, synth):
             nb = max(2, min(4, (1 << 30) // (8 * b * n)))
             xs = [x] + [x.clone() for _ in range(nb - 1)]
             ys = [torch.empty_like(x) for _ in range(nb)]
-            for mode in ("c64", "split_f16", "split_bf16", "f16"):
+            for mode in ("c64", "split_f16", "split_bf16", "split3_bf16", "f16"):
                 with fftc.Plan(n, b, fftc.FORWARD, mode) as p:
                     launches(f"{mode} N={n} batch {b}", [p], xs, ys, 3)
             del x, xs, ys
@@ -791,7 +791,7 @@ def profile_set(names, torch, fftc, synth):
         x = torch.from_numpy(synth.uniform_complex(synth.rng(1, 0), (ELEMS,), np.complex64)).to("cuda")
         xs = [x] + [x.clone() for _ in range(NBUF - 1)]
         ys = [torch.empty_like(x) for _ in range(NBUF)]
-        for n in ((1 << 20, 65536) if "two_pass" in names else ()) + ((16384,) if "c64_16384" in names else ()):
+        for n in ((1 << 20, 65536, 32768) if "two_pass" in names else ()) + ((16384,) if "c64_16384" in names else ()):
             with fftc.Plan(n, ELEMS // n, fftc.FORWARD, "c64") as p:
                 launches(f"c64 N={n} batch {ELEMS // n} ({p.describe()['variant']})", [p], xs, ys, 3)
         del x, xs, ys
