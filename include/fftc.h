@@ -332,10 +332,12 @@ fftc_status fftc_plan_mixed(const int64_t *n, int64_t count, int direction, int 
  * per launch, launches rotating over four input/output pairs that it
  * allocates and frees (1 GiB for complex64 at 2^24 elements), each launch
  * timed by its own events.  A candidate's time is the median of `reps`
- * launches (1 <= reps <= 100000; 20 or more gives stable picks); two
- * candidates tie unless their medians differ by more than twice the larger
- * relative interquartile range of their launches (at least 3%), and ties go
- * to fewer stages, then to the larger leading radix.  The winner is recorded
+ * launches (1 <= reps <= 100000; use 20 or more).  Every candidate whose
+ * median is within the tie window of the fastest -- twice the larger
+ * relative interquartile range of the two candidates' launches, and at least
+ * 3% -- counts as equally fast, and among those the list with fewer stages,
+ * then the one earlier in the planner's order, wins; picking from the whole
+ * tied set keeps the choice the same from run to run.  The winner is recorded
  * in the process's tuning database, which later plans for (n, dtype) use.
  * Returns the chosen list in radices[0..*count) and its median time per
  * launch in microseconds.  Synchronous.
@@ -380,8 +382,9 @@ fftc_status fftc_order_entry(int dtype, int i, int64_t *n, int *order, int *radi
  * every compiled (order, radix) for n, like fftc_autotune (median of `reps`
  * launches at the HBM-bound shape, rotating internal buffers).  Writes up to
  * `max` results (orders[i], radices[i] -- 0 for Stockham -- and us[i]), the
- * count, and the index of the fastest; a non-Stockham order wins only beyond
- * the tie window.  The winner is recorded in the tuning database, and
+ * count, and the index of the pick: Stockham unless it is outside the tie
+ * window (as for fftc_autotune) of the fastest candidate, else the first
+ * compiled order within that window of the fastest.  The winner is recorded in the tuning database, and
  * fftc_plan then uses that order for (n, dtype).
  */
 fftc_status fftc_autotune_orders(int64_t n, int64_t batch, int dtype, int reps, int *orders, int *radices,

@@ -82,15 +82,20 @@ fftc_status time_plan(fftc_plan_t p, DeviceBuffers& b, int reps, Timing* t) {
 // (run-to-run differences of the medians on one device reach about that).
 double tie_window(const Timing& a, const Timing& b) { return std::max(0.03, 2.0 * std::max(a.spread, b.spread)); }
 
-// a better than b: faster beyond the tie window, else fewer stages, else
-// larger leading radix
-bool better(const Timing& ta, const std::vector<int>& a, const Timing& tb, const std::vector<int>& b) {
-    const double w = tie_window(ta, tb);
-    if (ta.med < (1 - w) * tb.med) return true;
-    if (tb.med < (1 - w) * ta.med) return false;
-    if (a.size() != b.size()) return a.size() < b.size();
-    if (!a.empty() && !b.empty() && a[0] != b[0]) return a[0] > b[0];
-    return ta.med < tb.med;
+// The pick among timed candidates: every candidate within the tie window of
+// the fastest counts as equally fast, and among those the first by `prefer`
+// wins.  Choosing from the whole tied set, rather than comparing each
+// candidate with the best so far, keeps the pick the same from run to run
+// whenever the candidates' true times differ by less than the window.
+template <class Prefer>
+size_t pick(const std::vector<Timing>& t, Prefer prefer) {
+    size_t f = 0;
+    for (size_t i = 1; i < t.size(); ++i)
+        if (t[i].med < t[f].med) f = i;
+    size_t bi = f;
+    for (size_t i = 0; i < t.size(); ++i)
+        if (t[i].med <= (1 + tie_window(t[i], t[f])) * t[f].med && prefer(i, bi)) bi = i;
+    return bi;
 }
 
 }  // namespace
@@ -116,8 +121,8 @@ fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int* ra
         DeviceBuffers b;
         fftc_status sa = alloc_buffers(b, (size_t)tb * (size_t)n * cs, reps);
         if (sa != FFTC_OK) return sa;
-        std::vector<int> best;
-        Timing best_t;
+        std::vector<std::vector<int>> lists;
+        std::vector<Timing> times;
         for (const auto& rs : radix_candidates(n, 12)) {
             fftc_plan_t p = nullptr;
             fftc_status st = fftc_plan_radices(n, tb, FFTC_FORWARD, dtype, rs.data(), (int)rs.size(), &p);
@@ -126,12 +131,16 @@ fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int* ra
             st = time_plan(p, b, reps, &t);
             fftc_destroy_plan(p);
             if (st != FFTC_OK) return st;
-            if (best.empty() || better(t, rs, best_t, best)) {
-                best = rs;
-                best_t = t;
-            }
+            lists.push_back(rs);
+            times.push_back(t);
         }
-        if (best.empty()) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no candidate radix list could be planned");
+        if (lists.empty()) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no candidate radix list could be planned");
+        // among equally fast lists: fewer stages, then the planner's order
+        const size_t bi = pick(times, [&](size_t i, size_t j) {
+            return lists[i].size() != lists[j].size() ? lists[i].size() < lists[j].size() : i < j;
+        });
+        const std::vector<int>& best = lists[bi];
+        const Timing& best_t = times[bi];
         tune_record(n, dtype, best, best_t.med * 1e-3);
         *count = (int)best.size();
         if (best_us) *best_us = best_t.med;
@@ -180,9 +189,7 @@ fftc_status fftc_autotune_orders(int64_t n, int64_t batch, int dtype, int reps, 
             times.push_back(t);
         }
         // Stockham unless another order is faster beyond the tie window
-        size_t bi = 0;
-        for (size_t i = 1; i < cands.size(); ++i)
-            if (times[i].med < (1 - tie_window(times[i], times[bi])) * times[bi].med) bi = i;
+        const size_t bi = pick(times, [](size_t i, size_t j) { return i < j; });
         if (bi == 0)
             tune_record(n, dtype, stock, times[0].med * 1e-3);
         else
