@@ -4,6 +4,7 @@
 
 #include "internal.h"
 #include "stockham.h"
+#include "stockham_half.h"
 
 namespace fftc {
 
@@ -22,10 +23,17 @@ struct SpecInst {
     // left in LDS for the kernel to store
     static constexpr int TM = pick_t_for(kWorkgroupTarget, TPT, N, (int)sizeof(cplx<Real>), NR > 1);
     template <bool INV> using KM = SpecCfg<Real, N, TPT, TM, INV, true>;
+    // lists whose full LDS exchange fits one workgroup per CU run with the
+    // half-width exchange (two per CU)
+    static constexpr bool HALF = use_half_exchange<KF, Rs...>();
+    template <class KK> static const void* kernel() {
+        if constexpr (HALF)
+            return reinterpret_cast<const void*>(&stockham_spec_half<KK, Rs...>);
+        else
+            return reinterpret_cast<const void*>(&stockham_spec<KK, Rs...>);
+    }
     static SpecEntry entry(int dtype, int id) {
-        SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
-                    reinterpret_cast<const void*>(&stockham_spec<KF, Rs...>),
-                    reinterpret_cast<const void*>(&stockham_spec<KI, Rs...>), id};
+        SpecEntry e{dtype, N, NR, {Rs...}, TPT, T, kernel<KF>(), kernel<KI>(), id};
         e.tm = TM;
         return e;
     }

@@ -1,0 +1,111 @@
+// complex128 transforms whose full LDS exchange leaves room for one
+// workgroup per CU (N = 8192: 139 KB of LDS).  The exchange between two
+// stages moves the real parts through an LDS array of N reals, then the
+// imaginary parts through the same array, so a workgroup needs half the LDS
+// and two fit on a CU: while one exchanges, the other loads, computes or
+// stores.  An exchange takes four barriers instead of two.  (Measured at 2^24
+// elements: complex128 N = 8192 123 -> 101 us.  complex64 N = 16384 has the
+// same LDS footprint, but two 1024-thread workgroups per CU leave 64 VGPRs
+// per lane and the kernel then spills: 96 us against 66 us with the full
+// exchange, and 73 us with 512 threads of 32 elements.)
+//
+// Stage q (radix R after NS) is the Stockham step of the other kernels: the
+// thread's butterflies j = t + i TPT read x[j + r N/R], apply w_{NS R}^{r k}
+// (k = j mod NS), run DFT_R and write y[(j div NS) NS R + r NS + k].  Every
+// stage must give each thread the same N / TPT elements (TPT divides N / R).
+#pragma once
+#include "stockham.h"
+
+namespace fftc {
+
+template <int A, int... Rest> struct FirstOf {
+    static constexpr int value = A;
+};
+
+template <class K, int... Rs> constexpr bool half_even() { return (((K::N / Rs) % K::TPT == 0) && ...); }
+
+// Whether a compiled list runs with the half-width exchange.
+template <class K, int... Rs> constexpr bool use_half_exchange() {
+    return sizeof(typename K::RealT) == 8 && K::T == 1 && !K::STAGED && sizeof...(Rs) > 1 &&
+           half_even<K, Rs...>() && lds_len(K::N) * (int)sizeof(typename K::C) > kLdsMaxPerGroup / 2;
+}
+
+template <class K, int NS, int TWOFF, bool FIRST, int R, int... Rest>
+__device__ __forceinline__ void half_stages(GIn<typename K::C> gin, GOut<typename K::C> gout,
+                                            typename K::RealT* lds, const typename K::C* __restrict__ tw, int t,
+                                            typename K::C (&v)[K::N / K::TPT]) {
+    using C = typename K::C;
+    constexpr int N = K::N, TPT = K::TPT, NR = N / R, NB = NR / TPT;
+    constexpr bool LAST = sizeof...(Rest) == 0;
+    static_assert(NB * R == N / TPT, "every stage holds N / TPT elements per thread");
+    if constexpr (FIRST) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i * R + r] = gld<K::INV>(gin, t + i * TPT + r * NR);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if constexpr (NS > 1)
+            apply_twiddles<R, NS>(&v[i * R], (const FFTC_GLOBAL C*)tw + TWOFF + (t + i * TPT) % NS);
+        Codelet<R, C>::run(&v[i * R]);
+    }
+    if constexpr (LAST) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * TPT;
+            const int base = (j / NS) * NS * R + j % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) gst<K::INV>(gout, base + r * NS, v[i * R + r]);
+        }
+    } else {
+        constexpr int R2 = FirstOf<Rest...>::value;  // the next stage's radix
+        constexpr int NR2 = N / R2, NB2 = NR2 / TPT;
+        C w[N / TPT];
+        if constexpr (!FIRST) __syncthreads();  // the previous exchange's reads are done
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * TPT;
+            const int base = (j / NS) * NS * R + j % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = v[i * R + r].x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB2; ++i)
+#pragma unroll
+            for (int r = 0; r < R2; ++r) w[i * R2 + r].x = lds[lds_pad(t + i * TPT + r * NR2)];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * TPT;
+            const int base = (j / NS) * NS * R + j % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = v[i * R + r].y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB2; ++i)
+#pragma unroll
+            for (int r = 0; r < R2; ++r) w[i * R2 + r].y = lds[lds_pad(t + i * TPT + r * NR2)];
+        half_stages<K, NS * R, TWOFF + (R - 1) * NS, false, Rest...>(gin, gout, lds, tw, t, w);
+    }
+}
+
+// One transform per workgroup; two workgroups per CU (the second bound is in
+// waves per SIMD: two workgroups of TPT / 64 waves over the CU's 4 SIMDs).
+template <class K, int... Rs>
+__global__ void __launch_bounds__(K::TPT, 2 * K::TPT / 256)
+stockham_spec_half(const typename K::C* in, typename K::C* out, const typename K::C* __restrict__ tw,
+                   int64_t batch) {
+    using C = typename K::C;
+    static_assert(use_half_exchange<K, Rs...>(), "list not suited to the half-width exchange");
+    __shared__ typename K::RealT lds[lds_len(K::N)];
+    const int64_t b = blockIdx.x;  // one block per transform: b < batch
+    (void)batch;
+    C v[K::N / K::TPT];
+    half_stages<K, 1, 0, true, Rs...>(GIn<C>{(const FFTC_GLOBAL C*)(in + b * K::N)},
+                                      GOut<C>{(FFTC_GLOBAL C*)(out + b * K::N)}, lds, tw, (int)threadIdx.x, v);
+}
+
+}  // namespace fftc
