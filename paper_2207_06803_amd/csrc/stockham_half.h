@@ -24,10 +24,19 @@ template <int A, int... Rest> struct FirstOf {
 
 template <class K, int... Rs> constexpr bool half_even() { return (((K::N / Rs) % K::TPT == 0) && ...); }
 
-// Whether a compiled list runs with the half-width exchange.
+// Workgroups per CU with the half-width exchange: as many as the LDS holds,
+// up to 32 waves per CU.
+template <class K> constexpr int half_groups() {
+    constexpr int by_lds = kLdsMaxPerGroup / (lds_len(K::N) * (int)sizeof(typename K::RealT));
+    constexpr int by_waves = 32 / (K::TPT / 64);
+    return by_lds < by_waves ? by_lds : by_waves;
+}
+
+// Whether a compiled list runs with the half-width exchange: one transform
+// per workgroup whose full exchange takes more than a quarter of the LDS.
 template <class K, int... Rs> constexpr bool use_half_exchange() {
-    return sizeof(typename K::RealT) == 8 && K::T == 1 && !K::STAGED && sizeof...(Rs) > 1 &&
-           half_even<K, Rs...>() && lds_len(K::N) * (int)sizeof(typename K::C) > kLdsMaxPerGroup / 2;
+    return K::T == 1 && !K::STAGED && sizeof...(Rs) > 1 && K::TPT % 64 == 0 && half_even<K, Rs...>() &&
+           lds_len(K::N) * (int)sizeof(typename K::C) > kLdsMaxPerGroup / 4;
 }
 
 template <class K, int NS, int TWOFF, bool FIRST, int R, int... Rest>
@@ -61,41 +70,53 @@ __device__ __forceinline__ void half_stages(GIn<typename K::C> gin, GOut<typenam
     } else {
         constexpr int R2 = FirstOf<Rest...>::value;  // the next stage's radix
         constexpr int NR2 = N / R2, NB2 = NR2 / TPT;
+        // Padded LDS indices as one per-thread base plus compile-time offsets
+        // (immediate offsets of the LDS instructions, so the addresses take
+        // two registers instead of 2 N / TPT):
+        //   write  lds_pad(base + r NS) = lds_pad(base) + r NS + floor(r NS / 16),
+        //          exact when NS and R are powers of two (base mod 16 + (r NS
+        //          mod 16) never carries);
+        //   read   lds_pad(t + i TPT + r NR2) = lds_pad(t) + (i TPT + r NR2) 17 / 16,
+        //          exact when TPT and NR2 are multiples of 16.
+        static_assert((NS & (NS - 1)) == 0 && (R & (R - 1)) == 0, "power-of-two radices and strides");
+        static_assert(TPT % 16 == 0 && NR2 % 16 == 0, "reads at multiples of 16");
+        int wb[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * TPT;
+            wb[i] = lds_pad((j / NS) * NS * R + j % NS);
+        }
+        const int rb = lds_pad(t);
         C w[N / TPT];
         if constexpr (!FIRST) __syncthreads();  // the previous exchange's reads are done
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int j = t + i * TPT;
-            const int base = (j / NS) * NS * R + j % NS;
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = v[i * R + r].x;
-        }
+            for (int r = 0; r < R; ++r) lds[wb[i] + r * NS + (r * NS) / 16] = v[i * R + r].x;
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NB2; ++i)
 #pragma unroll
-            for (int r = 0; r < R2; ++r) w[i * R2 + r].x = lds[lds_pad(t + i * TPT + r * NR2)];
+            for (int r = 0; r < R2; ++r) w[i * R2 + r].x = lds[rb + (i * TPT + r * NR2) / 16 * 17];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int j = t + i * TPT;
-            const int base = (j / NS) * NS * R + j % NS;
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = v[i * R + r].y;
-        }
+            for (int r = 0; r < R; ++r) lds[wb[i] + r * NS + (r * NS) / 16] = v[i * R + r].y;
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NB2; ++i)
 #pragma unroll
-            for (int r = 0; r < R2; ++r) w[i * R2 + r].y = lds[lds_pad(t + i * TPT + r * NR2)];
+            for (int r = 0; r < R2; ++r) w[i * R2 + r].y = lds[rb + (i * TPT + r * NR2) / 16 * 17];
         half_stages<K, NS * R, TWOFF + (R - 1) * NS, false, Rest...>(gin, gout, lds, tw, t, w);
     }
 }
 
-// One transform per workgroup; two workgroups per CU (the second bound is in
-// waves per SIMD: two workgroups of TPT / 64 waves over the CU's 4 SIMDs).
+// One transform per workgroup, half_groups() workgroups per CU (the second
+// bound is in waves per SIMD: that many workgroups of TPT / 64 waves over the
+// CU's 4 SIMDs).
 template <class K, int... Rs>
-__global__ void __launch_bounds__(K::TPT, 2 * K::TPT / 256)
+__global__ void __launch_bounds__(K::TPT, (half_groups<K>() * K::TPT / 64 + 3) / 4)
 stockham_spec_half(const typename K::C* in, typename K::C* out, const typename K::C* __restrict__ tw,
                    int64_t batch) {
     using C = typename K::C;
