@@ -37,10 +37,14 @@ struct SpecInst {
         e.tm = TM;
         return e;
     }
+    template <class KK> static const void* reqs_kernel() {
+        if constexpr (HALF)
+            return reinterpret_cast<const void*>(&stockham_spec_half_reqs<KK, Rs...>);
+        else
+            return reinterpret_cast<const void*>(&stockham_spec_reqs<KK, Rs...>);
+    }
     static SpecEntry reqs_entry(int dtype) {
-        SpecEntry e{dtype, N, NR, {Rs...}, TPT, T,
-                    reinterpret_cast<const void*>(&stockham_spec_reqs<KF, Rs...>),
-                    reinterpret_cast<const void*>(&stockham_spec_reqs<KI, Rs...>), -1};
+        SpecEntry e{dtype, N, NR, {Rs...}, TPT, T, reqs_kernel<KF>(), reqs_kernel<KI>(), -1};
         return e;
     }
     // general accessors on both sides (planar or interleaved), and the

@@ -129,4 +129,22 @@ stockham_spec_half(const typename K::C* in, typename K::C* out, const typename K
                                       GOut<C>{(FFTC_GLOBAL C*)(out + b * K::N)}, lds, tw, (int)threadIdx.x, v);
 }
 
+// The serving runtime's several-requests launch (as stockham_spec_reqs) with
+// the same stages, so a request gives the same bits fused or alone.
+template <class K, int... Rs>
+__global__ void __launch_bounds__(K::TPT, (half_groups<K>() * K::TPT / 64 + 3) / 4)
+stockham_spec_half_reqs(ReqList L, const typename K::C* __restrict__ tw) {
+    using C = typename K::C;
+    static_assert(use_half_exchange<K, Rs...>(), "list not suited to the half-width exchange");
+    __shared__ typename K::RealT lds[lds_len(K::N)];
+    const int64_t blk = blockIdx.x;
+    int r = 0;
+    while (r + 1 < L.count && L.gstart[r + 1] <= blk) ++r;
+    const int64_t b = blk - L.gstart[r];  // one block per transform: b < L.batch[r]
+    C v[K::N / K::TPT];
+    half_stages<K, 1, 0, true, Rs...>(GIn<C>{(const FFTC_GLOBAL C*)(static_cast<const C*>(L.in[r]) + b * K::N)},
+                                      GOut<C>{(FFTC_GLOBAL C*)(static_cast<C*>(L.out[r]) + b * K::N)}, lds, tw,
+                                      (int)threadIdx.x, v);
+}
+
 }  // namespace fftc
