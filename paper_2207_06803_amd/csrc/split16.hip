@@ -77,13 +77,17 @@ __device__ __forceinline__ void split(float x, typename SplitTraits<MODE>::E* p)
     }
 }
 
-// cos / sin (2 pi t / 16), t = 0..15
-__device__ __forceinline__ void w16(int t, float* c, float* s) {
+// cos / sin (2 pi t / 16), t = 0..15.  Selects rather than an indexed
+// array: a runtime-indexed local table is placed in memory, and its loads
+// then stood in front of the transform's own HBM loads in every workgroup.
+__device__ __forceinline__ float cos16(int q) {  // cos of q sixteenths of a turn, q = 0..4
     const float c1 = 0.9238795325112867f, s1 = 0.3826834323650898f, h = 0.7071067811865476f;
-    const float cq[5] = {1.f, c1, h, s1, 0.f};  // cos of 0, 1, 2, 3, 4 sixteenths
-    const int q = t & 3, o = (t >> 2) & 3;      // t = 4 o + q
+    return q == 0 ? 1.f : q == 1 ? c1 : q == 2 ? h : q == 3 ? s1 : 0.f;
+}
+__device__ __forceinline__ void w16(int t, float* c, float* s) {
+    const int q = t & 3, o = (t >> 2) & 3;  // t = 4 o + q
     // angle = o pi/2 + q pi/8
-    float cc = cq[q], ss = cq[4 - q];
+    float cc = cos16(q), ss = cos16(4 - q);
     float rc, rs;
     switch (o) {
         case 0: rc = cc; rs = ss; break;
@@ -154,10 +158,13 @@ __device__ __forceinline__ void apply_next_twiddle(int p, float& re, float& im, 
 // (input r, real or imaginary part) as k = 2 r + c, so the lane holding
 // B[k][n], k = 8 (l / 16) + i, takes inputs r = 4 (l / 16) .. + 3 of
 // butterfly n whole: four complex values read from the interleaved LDS.
+template <int N, int W> constexpr int split_gpw() { return (N / 256 + W - 1) / W; }
+
 template <int N, int MODE, int NS, int R2, int NS2, int TW2, int W, bool INV, bool FIRST, bool LASTG>
-__device__ __forceinline__ void mfma_stage(float2* x, const float2* gin, float2* gout, const float2* __restrict__ tw,
+__device__ __forceinline__ void mfma_stage(float2* x, float2* gout, const float2* __restrict__ tw,
                                            const typename SplitTraits<MODE>::V (&a1)[3],
-                                           const typename SplitTraits<MODE>::V (&a2)[3]) {
+                                           const typename SplitTraits<MODE>::V (&a2)[3],
+                                           const float2 (&raw)[split_gpw<N, W>()][4]) {
     using T = SplitTraits<MODE>;
     using V = typename T::V;
     using E = typename T::E;
@@ -176,8 +183,8 @@ __device__ __forceinline__ void mfma_stage(float2* x, const float2* gin, float2*
             E parts[8][3];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                // the first stage reads HBM directly (16 lanes: 128 contiguous bytes)
-                const float2 v = FIRST ? ld_in<INV>(gin + j + (4 * g4 + i) * NB) : x[spad(j + (4 * g4 + i) * NB)];
+                // the first stage's inputs were loaded from HBM at the start
+                const float2 v = FIRST ? raw[gi][i] : x[spad(j + (4 * g4 + i) * NB)];
                 split<MODE>(v.x, parts[2 * i]);
                 split<MODE>(v.y, parts[2 * i + 1]);
             }
@@ -278,17 +285,18 @@ __device__ __forceinline__ void tail_stage(float2* x, float2* gout) {
 }
 
 template <int N, int MODE, int S, int NS, int TWOFF, int W, bool INV>
-__device__ __forceinline__ void run_mfma_stages(float2* x, const float2* gin, float2* gout,
+__device__ __forceinline__ void run_mfma_stages(float2* x, float2* gout,
                                                 const float2* __restrict__ tw,
                                                 const typename SplitTraits<MODE>::V (&a1)[3],
-                                                const typename SplitTraits<MODE>::V (&a2)[3]) {
+                                                const typename SplitTraits<MODE>::V (&a2)[3],
+                                                const float2 (&raw)[split_gpw<N, W>()][4]) {
     constexpr int S16 = split_stages16<N>();
     constexpr int RT = split_tail<N>();
     if constexpr (S < S16) {
         constexpr int TW2 = TWOFF + 15 * NS;  // next stage's twiddle segment
         constexpr int R2 = (S + 1 < S16) ? 16 : (RT > 1 ? RT : 0);
-        mfma_stage<N, MODE, NS, R2, NS * 16, TW2, W, INV, S == 0, R2 == 0>(x, gin, gout, tw, a1, a2);
-        run_mfma_stages<N, MODE, S + 1, NS * 16, TW2, W, INV>(x, gin, gout, tw, a1, a2);
+        mfma_stage<N, MODE, NS, R2, NS * 16, TW2, W, INV, S == 0, R2 == 0>(x, gout, tw, a1, a2, raw);
+        run_mfma_stages<N, MODE, S + 1, NS * 16, TW2, W, INV>(x, gout, tw, a1, a2, raw);
     } else if constexpr (RT > 1) {
         tail_stage<N, RT, NS, 64 * W, INV>(x, gout);
     }
@@ -314,6 +322,21 @@ split_fft(const float2* in, float2* out, const float2* __restrict__ tw, int64_t 
     const float2* x = in + b * N;
     float2* y = out + b * N;
     const int t = (int)threadIdx.x;
+    // the first stage's inputs, loaded before anything else so the HBM
+    // latency overlaps the operand setup below (16 lanes: 128 contiguous
+    // bytes; a wave past the last group loads group 0 and discards it)
+    constexpr int GPW = split_gpw<N, W>();
+    float2 raw[GPW][4];
+    {
+        const int lane = t & 63, wave = t >> 6, n = lane & 15, g4 = lane >> 4;
+#pragma unroll
+        for (int gi = 0; gi < GPW; ++gi) {
+            const int grp = wave + gi * W;
+            const int j = (grp < N / 256 ? grp : 0) * 16 + n;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) raw[gi][i] = ld_in<INV>(x + j + (4 * g4 + i) * (N / 16));
+        }
+    }
     // operands A1 = [Wr | -Wi], A2 = [Wi | Wr] for this lane, split, with the
     // contraction index k = 2 r + c (c = 0: real parts, 1: imaginary parts)
     V a1[3], a2[3];
@@ -339,7 +362,7 @@ split_fft(const float2* in, float2* out, const float2* __restrict__ tw, int64_t 
         }
     }
     // the first stage reads HBM and the last writes it
-    run_mfma_stages<N, MODE, 0, 1, 0, W, INV>(xs, x, y, tw, a1, a2);
+    run_mfma_stages<N, MODE, 0, 1, 0, W, INV>(xs, y, tw, a1, a2, raw);
 }
 
 // ---------------------------------------------------------------------------
