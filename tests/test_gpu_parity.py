@@ -119,6 +119,28 @@ def test_config2_full_size_sampled(n, dtype):
         assert rel.max() <= 2 * tol_for(n, dtype), rel.max()
 
 
+@pytest.mark.parametrize("n,dtype", [(8192, "c64"), (16384, "c64"), (4096, "c128"), (8192, "c128")])
+def test_half_exchange_full_size_sampled(n, dtype):
+    # the lengths whose kernels exchange real and imaginary parts through LDS
+    # separately, at the benchmarked launch size (2^24 elements, several
+    # workgroups per CU): sampled transforms against the oracle, Parseval on
+    # every transform, both directions
+    batch = (1 << 24) // n
+    g = synth.rng(1, n, 2 if dtype == "c64" else 3)
+    x = synth.uniform_complex(g, (batch, n), np_dtype(dtype))
+    rows = np.unique(np.r_[0, batch - 1, g.integers(0, batch, 2)])
+    for d in (FWD, INV):
+        say(f"half-exchange full n={n} batch={batch} {dtype} dir={d}")
+        with fftc.Plan(n, batch, d, dtype) as p:
+            y = run_plan(p, x)
+        err = rel_l2(y[rows], oracle.dft(x[rows], d))
+        say(f"  sampled rows {rows.tolist()}: max rel L2 {err.max():.3e}")
+        assert err.max() <= tol_for(n, dtype), err.max()
+        ex = (np.abs(x.astype(np.complex128)) ** 2).sum(axis=1) * n
+        ey = (np.abs(y.astype(np.complex128)) ** 2).sum(axis=1)
+        assert (np.abs(ey - ex) / ex).max() <= 2 * tol_for(n, dtype)
+
+
 def test_inplace_single_kernel():
     for n, dtype in ((1024, "c64"), (3584, "c64"), (4096, "c128"), (64, "c64")):
         check(n, 37, FWD, dtype, inplace=True)
