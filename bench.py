@@ -145,6 +145,47 @@ class Timer:
 HEADLINE_SOURCES = ("codelets.h", "cplx.h", "kconfig.h", "stockham.h", "spec_table.h", "exec.hip", "planner.cpp")
 
 
+SPLIT_SOURCES = ("split16.hip", "codelets.h")
+
+
+def file_hash(names):
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2207_06803_amd", "csrc")
+    for name in names:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+SPLIT_MODE_NUMBER = {"split_f16": 2, "split_bf16": 3, "split3_bf16": 4, "f16": 5}
+
+
+def split_mfma_busy():
+    """MfmaUtil of the split-precision kernels at batch 8192 from the counter
+    report in profiles/hot_path_counters.md, {(N, mode): fraction}, or {} if
+    that report was made from other split-kernel sources (its recorded hash)."""
+    import re
+    path = os.path.join(ROOT, "profiles", "hot_path_counters.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return {}
+    m = re.search(r"split-kernel source hash: ([0-9a-f]{16})", text)
+    if not m or m.group(1) != file_hash(SPLIT_SOURCES):
+        return {}
+    out = {}
+    num_to_mode = {v: k for k, v in SPLIT_MODE_NUMBER.items()}
+    for line in text.splitlines():
+        r = re.match(r"\| `void fftc::split_fft<(\d+), (\d), false>` \|", line)
+        if not r or int(r.group(2)) not in num_to_mode:
+            continue
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) > 12 and cells[12].endswith("%"):
+            out[(int(r.group(1)), num_to_mode[int(r.group(2))])] = float(cells[12][:-1]) / 100
+    return out
+
+
 def source_hash():
     import re
     h = hashlib.sha256()
@@ -371,6 +412,7 @@ def config4(torch, fftc, synth, timer):
     out = {}
     modes = ("c64", "split_f16", "split_bf16", "split3_bf16", "f16")
     mfma_per_group = {"split_f16": 6, "split_bf16": 6, "split3_bf16": 12, "f16": 2}
+    busy = split_mfma_busy()
     for n in (1024, 4096, 16384):
         b = 8192
         xh = synth.gaussian_complex(synth.rng(4, n), (b * n,), np.complex64)
@@ -418,6 +460,9 @@ def config4(torch, fftc, synth, timer):
                     mf = groups * mfma_per_group[mode] * 2 * 16 * 16 * 32 * b
                     e["mfma_tflops"] = mf / (ms * 1e-3) / 1e12
                     e["mfma_util"] = e["mfma_tflops"] / MFMA_PEAK_TFLOPS["f16"]
+                    # the matrix cores' busy share from the profiler's counters
+                    # (SQ_VALU_MFMA_BUSY_CYCLES), for the same launch
+                    e["mfma_busy_counter"] = busy.get((n, mode))
                 row[mode] = e
         row["rotating_buffers"] = nb
         row["oracle_sample_rows"] = int(len(rows))

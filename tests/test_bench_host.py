@@ -67,3 +67,19 @@ def test_counter_report_needs_counter_run():
     r = subprocess.run([sys.executable, os.path.join(os.path.dirname(bench.__file__), "bench.py"),
                         "--counter-report", "only_trace.db"], capture_output=True, text=True)
     assert r.returncode != 0 and "counter run" in r.stderr
+
+
+def test_split_mfma_busy_from_profile():
+    """The precision study quotes the counters' MfmaUtil for its split-precision
+    launches from the committed report, guarded by the split kernel's source
+    hash recorded there."""
+    busy = bench.split_mfma_busy()
+    import re
+    text = open(os.path.join(bench.ROOT, "profiles", "hot_path_counters.md")).read()
+    m = re.search(r"split-kernel source hash: ([0-9a-f]{16})", text)
+    if not m or m.group(1) != bench.file_hash(bench.SPLIT_SOURCES):
+        assert busy == {}
+        pytest.skip("the counter report predates the current split-kernel sources")
+    assert set(busy) == {(n, mode) for n in (1024, 4096, 16384) for mode in bench.SPLIT_MODE_NUMBER}
+    assert all(0.0 < v < 1.0 for v in busy.values())
+    assert busy[(4096, "split3_bf16")] > busy[(4096, "f16")]  # twice the products per group
