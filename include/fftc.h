@@ -90,7 +90,8 @@ fftc_status fftc_plan(int64_t n, int64_t batch, int direction, int dtype, fftc_p
 /*
  * As fftc_plan with an explicit Stockham radix list r[0..count) whose
  * product is n; every radix must be one of 2, 3, 4, 5, 7, 8, 16.  Only
- * single-kernel lengths (see fftc_max_single_n) are accepted.
+ * single-kernel lengths (see fftc_max_single_n) are accepted; for the wide
+ * lengths only their compiled lists (fftc_compiled_entry).
  */
 fftc_status fftc_plan_radices(int64_t n, int64_t batch, int direction, int dtype,
                               const int *radices, int count, fftc_plan_t *plan_out);
@@ -277,21 +278,30 @@ fftc_status fftc_factorize(int64_t n, int dtype, int *radices, int max_count, in
 
 /*
  * Host-only: the candidate Stockham radix lists for single-kernel length n,
- * in the planner's preference order (the autotuner times these).  List i is
+ * in the planner's preference order (the autotuner times these; for a wide
+ * length it times the compiled lists instead).  List i is
  * radices[i * 16 .. i * 16 + lens[i]); at most max_lists lists are written,
  * *nlists is how many there are (up to 12).
  */
 fftc_status fftc_candidates(int64_t n, int *radices, int *lens, int max_lists, int *nlists);
 
 /*
- * Host-only: the radix lists compiled as specialised kernels for dtype.
+ * Host-only: the radix lists compiled as specialised kernels for dtype,
+ * the wide lengths' lists (see fftc_max_single_n) last.
  * Entry i (0 <= i < fftc_compiled_count(dtype)) has length *n and list
  * radices[0..*count); max_count is the capacity of radices (>= 8).
  */
 int fftc_compiled_count(int dtype);
 fftc_status fftc_compiled_entry(int dtype, int i, int64_t *n, int *radices, int max_count, int *count);
 
-/* Host-only: largest n that runs as one kernel for dtype. */
+/*
+ * Host-only: every supported n up to this value (complex64 16384,
+ * complex128 8192) runs as one kernel for dtype.  Above it, the wide lengths
+ * complex64 32768 and complex128 16384 also run as one kernel (one transform
+ * per 1024-thread workgroup, its stages exchanging real and imaginary parts
+ * in turn through 139 KB of LDS, from their compiled lists only); every other
+ * n runs as the two passes of Eq. 2.
+ */
 int64_t fftc_max_single_n(int dtype);
 
 /*
@@ -327,7 +337,8 @@ fftc_status fftc_plan_mixed(const int64_t *n, int64_t count, int direction, int 
 /*
  * Autotuner (the planner the paper names as missing, Section VI; different
  * factorisations suit different hardware, Section I).  Times every
- * candidate Stockham radix list for single-kernel length n, forward, on an
+ * candidate Stockham radix list for single-kernel length n (for a wide
+ * length, each of its compiled lists), forward, on an
  * internal stream, at the HBM-bound shape: max(batch, 2^24 / n) transforms
  * per launch, launches rotating over four input/output pairs that it
  * allocates and frees (1 GiB for complex64 at 2^24 elements), each launch

@@ -120,6 +120,15 @@ const SpecEntry* find_spec(int dtype, int64_t n, const std::vector<int>& rs) {
             if (same) return &e;
         }
     }
+    int cnt = 0;
+    const SpecEntry* tab = wide_table(dtype, &cnt);
+    for (int i = 0; i < cnt; ++i) {
+        const SpecEntry& e = tab[i];
+        if (e.n != n || e.nr != (int)rs.size()) continue;
+        bool same = true;
+        for (int q = 0; q < e.nr; ++q) same = same && e.radices[q] == rs[q];
+        if (same) return &e;
+    }
     return nullptr;
 }
 
@@ -151,8 +160,12 @@ static fftc_status shape_single(fftc_plan_s* p, const std::vector<int>& rs) {
         launch_shape(p->n, rs, (int)cs, &p->tpt, &p->t);
         p->variant = FFTC_VARIANT_SINGLE_GENERIC;
     }
+    if (p->n > max_single_n(p->dtype) && !p->spec)
+        return fail(FFTC_ERR_UNSUPPORTED_SIZE, "n = " + std::to_string(p->n) +
+                                                   " runs only its compiled radix lists (fftc_compiled_entry)");
     if (p->tpt * p->t > 1024) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "radix list needs more than 1024 threads");
-    p->lds_bytes = rs.size() > 1 ? (size_t)p->t * lds_len((int)p->n) * cs : 0;
+    // the half-width exchange moves one real per element at a time
+    p->lds_bytes = rs.size() > 1 ? (size_t)p->t * lds_len((int)p->n) * cs / (p->spec && p->spec->half ? 2 : 1) : 0;
     if (p->lds_bytes > (size_t)kLdsMaxPerGroup) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "transform too large for LDS");
     fill_gen_desc(p->n, rs, p->tpt, p->t, 0, &p->gdesc);
     return FFTC_OK;
@@ -222,13 +235,17 @@ static fftc_status check_plan_args(int64_t n, int64_t batch, int direction, int 
         return fail(FFTC_ERR_UNSUPPORTED_SIZE,
                     "n = " + std::to_string(n) + " unsupported (need 1 <= n <= 2^20 with prime factors <= 7)");
     if (batch > (int64_t(1) << 40) / n) return fail(FFTC_ERR_INVALID_ARG, "batch * n too large");
-    if (radices && n > max_single_n(dtype))
+    if (radices && !single_kernel(n, dtype))
         return fail(FFTC_ERR_INVALID_ARG, "explicit radix lists are for single-kernel lengths only");
     if (radices) {
         if (count < 0 || count > kMaxStages || (count == 0 && n != 1))
             return fail(FFTC_ERR_INVALID_ARG, "bad radix count");
-        fftc_status cr = check_radices(n, std::vector<int>(radices, radices + count));
+        const std::vector<int> rs(radices, radices + count);
+        fftc_status cr = check_radices(n, rs);
         if (cr != FFTC_OK) return cr;
+        if (n > max_single_n(dtype) && !find_spec(dtype, n, rs))
+            return fail(FFTC_ERR_UNSUPPORTED_SIZE, "n = " + std::to_string(n) +
+                                                       " runs only its compiled radix lists (fftc_compiled_entry)");
     }
     return FFTC_OK;
 }
@@ -251,7 +268,7 @@ fftc_status shape_plan(fftc_plan_s* p, const int* radices, int count, std::vecto
         *entries = stage_segments(p->radices, 0, segs);
         return FFTC_OK;
     }
-    if (n <= max_single_n(dtype)) {
+    if (single_kernel(n, dtype)) {
         std::vector<int> rs;
         if (radices) {
             rs.assign(radices, radices + count);
@@ -854,7 +871,7 @@ fftc_status fftc_factorize(int64_t n, int dtype, int* radices, int max_count, in
     if (n < 1 || n > max_total_n(dtype) || !is_7smooth(n)) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "unsupported n");
     std::vector<int> rs;
     int64_t m = 0, k = 0;
-    if (n <= max_single_n(dtype)) {
+    if (single_kernel(n, dtype)) {
         if (n > 1) rs = choose_radices(n, dtype);
     } else {
         if (!two_pass_split(n, dtype, &m, &k)) return fail(FFTC_ERR_UNSUPPORTED_SIZE, "no split");
@@ -893,7 +910,9 @@ int fftc_compiled_count(int dtype) {
         spec_part(dtype, part, &cnt);
         total += cnt;
     }
-    return total;
+    int wide = 0;
+    wide_table(dtype, &wide);
+    return total + wide;
 }
 
 fftc_status fftc_compiled_entry(int dtype, int i, int64_t* n, int* radices, int max_count, int* count) {
@@ -913,6 +932,16 @@ fftc_status fftc_compiled_entry(int dtype, int i, int64_t* n, int* radices, int 
             return FFTC_OK;
         }
         base += cnt;
+    }
+    int wide = 0;
+    const SpecEntry* tab = wide_table(dtype, &wide);
+    if (i >= base && i < base + wide) {
+        const SpecEntry& e = tab[i - base];
+        if (e.nr > max_count) return fail(FFTC_ERR_INVALID_ARG, "max_count too small");
+        *n = e.n;
+        *count = e.nr;
+        for (int q = 0; q < e.nr; ++q) radices[q] = e.radices[q];
+        return FFTC_OK;
     }
     return fail(FFTC_ERR_INVALID_ARG, "index out of range");
 }

@@ -48,7 +48,13 @@ struct Range {
 
 // ---- factorisation (planner.cpp, host only) -------------------------------
 bool is_7smooth(int64_t n);
+// Every supported length up to max_single_n runs as one kernel (generic or
+// compiled); above it, the lengths with compiled wide lists do too (complex64
+// 32768, complex128 16384), the rest run as two passes of Eq. 2.
 int64_t max_single_n(int dtype);
+bool single_kernel(int64_t n, int dtype);
+// The compiled wide lists of n, fastest measured first (empty for other n).
+std::vector<std::vector<int>> wide_lists(int64_t n, int dtype);
 int64_t max_total_n(int dtype);
 // Radix lists that multiply to n, in preference order (first = heuristic pick).
 std::vector<std::vector<int>> radix_candidates(int64_t n, int max_lists = 12);
@@ -56,7 +62,9 @@ std::vector<std::vector<int>> radix_candidates(int64_t n, int max_lists = 12);
 void launch_shape(int64_t n, const std::vector<int>& rs, int csize, int* tpt, int* t);
 // Two-pass split n = m k (pass 1: k columns of length m; pass 2: m of length k).
 bool two_pass_split(int64_t n, int dtype, int64_t* m, int64_t* k);
-// Radix list a plan uses: the tuning database's entry, else candidates[0].
+// Radix list a plan uses: the tuning database's entry, else candidates[0]
+// (for a wide length: a recorded list only if it is compiled, else the first
+// wide list).
 std::vector<int> choose_radices(int64_t n, int dtype);
 // Tuning database: best radix list for (n, dtype), if recorded.
 bool tune_lookup(int64_t n, int dtype, std::vector<int>* rs);
@@ -83,6 +91,7 @@ struct SpecEntry {
     const void* tile_inv = nullptr;
     int tile_tpt = 0, tile_tc = 0;
     int tm = 0;  // transforms per 256-thread workgroup in the mixed kernel's body
+    bool half = false;  // exchanges through LDS in half width (real, then imaginary parts)
     // layout entries, both sides interleaved (one vector access per element)
     const void* il_fwd = nullptr;
     const void* il_inv = nullptr;
@@ -103,6 +112,9 @@ const SpecEntry* find_spec(int dtype, int64_t n, const std::vector<int>& rs);
 const SpecEntry* find_layout(int dtype, int64_t n, const std::vector<int>& rs);
 // Several-requests kernels (one launch for requests of one length).
 const SpecEntry* find_serve(int dtype, int64_t n, const std::vector<int>& rs);
+// Wide single-kernel lists (spec_wide.hip): plain and several-requests kernels.
+const SpecEntry* wide_table(int dtype, int* count);
+const SpecEntry* wide_serve_table(int dtype, int* count);
 
 // Two-pass column kernels with compiled bodies (fourstep_c64/c128.hip):
 // the four kernels (pass x direction) of one column length.

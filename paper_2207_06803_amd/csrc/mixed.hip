@@ -70,7 +70,7 @@ fftc_status build_mixed(fftc_plan_s* p, const int64_t* n, int64_t count) {
         const int64_t per = rs.size() > 1 ? lds_len((int)len) : 0;
         const SpecEntry* spec = len > 1 ? find_spec(dtype, len, rs) : nullptr;
         int64_t ldsn = per;
-        if (spec && spec->tpt * spec->tm <= kMixedThreads) {
+        if (spec && spec->id >= 0 && spec->tpt * spec->tm <= kMixedThreads) {
             // compiled body: its shape for 256-thread workgroups; short lists stage through LDS
             tpt = spec->tpt;
             t = spec->tm;

@@ -30,6 +30,19 @@ bool is_7smooth(int64_t n) {
 }
 
 int64_t max_single_n(int dtype) { return dtype == FFTC_C128 ? 8192 : 16384; }
+
+std::vector<std::vector<int>> wide_lists(int64_t n, int dtype) {
+    std::vector<std::vector<int>> out;
+    int cnt = 0;
+    const SpecEntry* tab = wide_table(dtype, &cnt);
+    for (int i = 0; i < cnt; ++i)
+        if (tab[i].n == n) out.emplace_back(tab[i].radices, tab[i].radices + tab[i].nr);
+    return out;
+}
+
+bool single_kernel(int64_t n, int dtype) {
+    return n <= max_single_n(dtype) || (n <= max_total_n(dtype) && !wide_lists(n, dtype).empty());
+}
 int64_t max_total_n(int /*dtype*/) { return int64_t(1) << 20; }
 
 static void pow2_multisets(int a, std::vector<int>& cur, int maxpart,
@@ -107,7 +120,7 @@ void launch_shape(int64_t n, const std::vector<int>& rs, int csize, int* tpt, in
 
 bool two_pass_split(int64_t n, int dtype, int64_t* m_out, int64_t* k_out) {
     (void)dtype;
-    if (n <= max_single_n(dtype) || n > max_total_n(dtype) || !is_7smooth(n)) return false;
+    if (single_kernel(n, dtype) || n > max_total_n(dtype) || !is_7smooth(n)) return false;
     // most balanced m k = n with both factors <= 1024 (the column tile of a
     // pass holds T columns of one length in LDS)
     int64_t best_m = 0;
@@ -127,6 +140,11 @@ bool two_pass_split(int64_t n, int dtype, int64_t* m_out, int64_t* k_out) {
 
 std::vector<int> choose_radices(int64_t n, int dtype) {
     std::vector<int> rs;
+    if (n > max_single_n(dtype)) {  // a wide length runs its compiled lists only
+        const auto w = wide_lists(n, dtype);
+        if (tune_lookup(n, dtype, &rs) && std::find(w.begin(), w.end(), rs) != w.end()) return rs;
+        return w.empty() ? std::vector<int>() : w[0];
+    }
     if (tune_lookup(n, dtype, &rs)) return rs;
     auto c = radix_candidates(n, 1);
     return c.empty() ? rs : c[0];

@@ -21,14 +21,17 @@ const SpecEntry* serve_table_c64(int* count);
 const SpecEntry* serve_table_c128(int* count);
 
 const SpecEntry* find_serve(int dtype, int64_t n, const std::vector<int>& rs) {
-    int cnt = 0;
-    const SpecEntry* tab = dtype == FFTC_C128 ? serve_table_c128(&cnt) : serve_table_c64(&cnt);
-    for (int i = 0; i < cnt; ++i) {
-        const SpecEntry& e = tab[i];
-        if (e.n != n || e.nr != (int)rs.size()) continue;
-        bool same = true;
-        for (int q = 0; q < e.nr; ++q) same = same && e.radices[q] == rs[q];
-        if (same) return &e;
+    for (int w = 0; w < 2; ++w) {  // the powers of two's preferred lists, then the wide lists
+        int cnt = 0;
+        const SpecEntry* tab = w ? wide_serve_table(dtype, &cnt)
+                                 : (dtype == FFTC_C128 ? serve_table_c128(&cnt) : serve_table_c64(&cnt));
+        for (int i = 0; i < cnt; ++i) {
+            const SpecEntry& e = tab[i];
+            if (e.n != n || e.nr != (int)rs.size()) continue;
+            bool same = true;
+            for (int q = 0; q < e.nr; ++q) same = same && e.radices[q] == rs[q];
+            if (same) return &e;
+        }
     }
     return nullptr;
 }

@@ -35,6 +35,7 @@ struct SpecInst {
     static SpecEntry entry(int dtype, int id) {
         SpecEntry e{dtype, N, NR, {Rs...}, TPT, T, kernel<KF>(), kernel<KI>(), id};
         e.tm = TM;
+        e.half = HALF;
         return e;
     }
     template <class KK> static const void* reqs_kernel() {
@@ -45,6 +46,7 @@ struct SpecInst {
     }
     static SpecEntry reqs_entry(int dtype) {
         SpecEntry e{dtype, N, NR, {Rs...}, TPT, T, reqs_kernel<KF>(), reqs_kernel<KI>(), -1};
+        e.half = HALF;
         return e;
     }
     // general accessors on both sides (planar or interleaved), and the
@@ -62,6 +64,36 @@ struct SpecInst {
         e.pi_inv = reinterpret_cast<const void*>(&stockham_spec_layout<KI, GA, GI, Rs...>);
         e.ip_fwd = reinterpret_cast<const void*>(&stockham_spec_layout<KF, GI, GA, Rs...>);
         e.ip_inv = reinterpret_cast<const void*>(&stockham_spec_layout<KI, GI, GA, Rs...>);
+        return e;
+    }
+};
+
+// Lengths whose full LDS exchange exceeds a workgroup's LDS (complex64
+// N = 32768 and complex128 N = 16384 take 278 KB): one 1024-thread workgroup
+// per transform, N / 1024 elements per thread, with the half-width exchange
+// (139 KB, one workgroup per CU).  Against the two passes of Eq. 2 these
+// lengths would otherwise take, every element crosses HBM once each way
+// instead of twice.  No mixed-kernel body (id -1).
+template <typename Real, int N, int... Rs>
+struct WideSpecInst {
+    static constexpr int TPT = 1024;
+    using KF = SpecCfg<Real, N, TPT, 1, false>;
+    using KI = SpecCfg<Real, N, TPT, 1, true>;
+    static_assert(use_half_exchange<KF, Rs...>(), "wide lists run with the half-width exchange");
+    static_assert(N / TPT <= 32, "at most 32 elements per thread");
+    static_assert(lds_len(N) * (int)sizeof(Real) <= kLdsMaxPerGroup, "half-width exchange LDS");
+    static SpecEntry entry(int dtype) {
+        SpecEntry e{dtype, N, (int)sizeof...(Rs), {Rs...}, TPT, 1,
+                    reinterpret_cast<const void*>(&stockham_spec_half<KF, Rs...>),
+                    reinterpret_cast<const void*>(&stockham_spec_half<KI, Rs...>), -1};
+        e.half = true;
+        return e;
+    }
+    static SpecEntry reqs_entry(int dtype) {
+        SpecEntry e{dtype, N, (int)sizeof...(Rs), {Rs...}, TPT, 1,
+                    reinterpret_cast<const void*>(&stockham_spec_half_reqs<KF, Rs...>),
+                    reinterpret_cast<const void*>(&stockham_spec_half_reqs<KI, Rs...>), -1};
+        e.half = true;
         return e;
     }
 };

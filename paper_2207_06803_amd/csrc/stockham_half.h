@@ -1,13 +1,17 @@
-// complex128 transforms whose full LDS exchange leaves room for one
-// workgroup per CU (N = 8192: 139 KB of LDS).  The exchange between two
-// stages moves the real parts through an LDS array of N reals, then the
-// imaginary parts through the same array, so a workgroup needs half the LDS
-// and two fit on a CU: while one exchanges, the other loads, computes or
-// stores.  An exchange takes four barriers instead of two.  (Measured at 2^24
-// elements: complex128 N = 8192 123 -> 101 us.  complex64 N = 16384 has the
-// same LDS footprint, but two 1024-thread workgroups per CU leave 64 VGPRs
-// per lane and the kernel then spills: 96 us against 66 us with the full
-// exchange, and 73 us with 512 threads of 32 elements.)
+// Transforms whose full LDS exchange leaves room for one workgroup per CU
+// (complex128 N = 8192: 139 KB of LDS) or does not fit at all (complex64
+// N = 32768, complex128 N = 16384: 278 KB).  The exchange between two stages
+// moves the real parts through an LDS array of N reals, then the imaginary
+// parts through the same array, so a workgroup needs half the LDS: two fit on
+// a CU where one did (while one exchanges, the other loads, computes or
+// stores), and the longest lengths run in one kernel instead of the two
+// passes of Eq. 2.  An exchange takes four barriers instead of two.
+// (Measured at 2^24 elements: complex128 N = 8192 123 -> 101 us; complex64
+// N = 32768 107 -> 76 us and complex128 N = 16384 237 -> 125 us against two
+// passes.  complex64 N = 16384 has the same LDS footprint as complex128
+// 8192, but two 1024-thread workgroups per CU leave 64 VGPRs per lane and the
+// kernel then spills: 96 us against 66 us with the full exchange, and 73 us
+// with 512 threads of 32 elements.)
 //
 // Stage q (radix R after NS) is the Stockham step of the other kernels: the
 // thread's butterflies j = t + i TPT read x[j + r N/R], apply w_{NS R}^{r k}

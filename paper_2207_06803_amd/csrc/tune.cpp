@@ -112,9 +112,9 @@ fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int* ra
     if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
     if (batch < 1 || reps < 1) return fail(FFTC_ERR_INVALID_ARG, "batch and reps must be >= 1");
     if (reps > 100000) return fail(FFTC_ERR_INVALID_ARG, "reps must be <= 100000");
-    if (n < 2 || n > max_single_n(dtype) || !is_7smooth(n))
-        return fail(FFTC_ERR_UNSUPPORTED_SIZE, "autotune takes single-kernel lengths 2.." +
-                                                   std::to_string(max_single_n(dtype)));
+    if (n < 2 || !single_kernel(n, dtype) || !is_7smooth(n))
+        return fail(FFTC_ERR_UNSUPPORTED_SIZE, "autotune takes single-kernel lengths (2.." +
+                                                   std::to_string(max_single_n(dtype)) + " and the wide lengths)");
     try {
         const size_t cs = dtype == FFTC_C128 ? 16 : 8;
         const int64_t tb = tune_batch(n, batch);
@@ -123,7 +123,8 @@ fftc_status fftc_autotune(int64_t n, int64_t batch, int dtype, int reps, int* ra
         if (sa != FFTC_OK) return sa;
         std::vector<std::vector<int>> lists;
         std::vector<Timing> times;
-        for (const auto& rs : radix_candidates(n, 12)) {
+        // a wide length: its compiled lists (the only ones it runs)
+        for (const auto& rs : n > max_single_n(dtype) ? wide_lists(n, dtype) : radix_candidates(n, 12)) {
             fftc_plan_t p = nullptr;
             fftc_status st = fftc_plan_radices(n, tb, FFTC_FORWARD, dtype, rs.data(), (int)rs.size(), &p);
             if (st != FFTC_OK) continue;  // list does not fit this device's limits
@@ -159,9 +160,9 @@ fftc_status fftc_autotune_orders(int64_t n, int64_t batch, int dtype, int reps, 
     if (dtype != FFTC_C64 && dtype != FFTC_C128) return fail(FFTC_ERR_INVALID_ARG, "bad dtype");
     if (batch < 1 || reps < 1) return fail(FFTC_ERR_INVALID_ARG, "batch and reps must be >= 1");
     if (reps > 100000) return fail(FFTC_ERR_INVALID_ARG, "reps must be <= 100000");
-    if (n < 2 || n > max_single_n(dtype) || !is_7smooth(n))
-        return fail(FFTC_ERR_UNSUPPORTED_SIZE, "autotune takes single-kernel lengths 2.." +
-                                                   std::to_string(max_single_n(dtype)));
+    if (n < 2 || !single_kernel(n, dtype) || !is_7smooth(n))
+        return fail(FFTC_ERR_UNSUPPORTED_SIZE, "autotune takes single-kernel lengths (2.." +
+                                                   std::to_string(max_single_n(dtype)) + " and the wide lengths)");
     try {
         const size_t cs = dtype == FFTC_C128 ? 16 : 8;
         const int64_t tb = std::min<int64_t>(tune_batch(n, batch), int64_t(1) << 31);

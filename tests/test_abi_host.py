@@ -64,12 +64,39 @@ def test_planner_lists_multiply_to_dft(n):
 
 
 def test_two_pass_split():
-    for n in (32768, 65536, 1 << 18, 1 << 20, 3 * 16384, 7 * 4096 * 2):
+    # lengths past the single-kernel limit without a compiled wide list,
+    # including 7-smooth lengths below the complex64 wide length
+    for n in (3 * 8192, 5 * 4096, 7 * 4096, 65536, 1 << 18, 1 << 20, 3 * 16384, 7 * 4096 * 2):
         rs, m = fftc.factorize(n, "c64")
         assert m > 0 and n % m == 0 and m <= 1024 and n // m <= 1024, (n, m)
         assert int(np.prod(rs)) == n
-    rs, m = fftc.factorize(16384, "c128")
-    assert m > 0
+    for n in (3 * 4096, 32768):
+        rs, m = fftc.factorize(n, "c128")
+        assert m > 0
+
+
+WIDE = {"c64": 32768, "c128": 16384}
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_wide_length_is_one_kernel(dtype):
+    """complex64 32768 and complex128 16384 (past fftc_max_single_n) run as
+    one kernel with their first compiled wide list; a list that is not
+    compiled for them is refused on the host."""
+    n = WIDE[dtype]
+    assert n > fftc.max_single_n(dtype)
+    wide = [tuple(rs) for m, rs in fftc.compiled_lists(dtype) if m == n]
+    assert len(wide) == 3 and all(int(np.prod(rs)) == n and len(rs) == 4 for rs in wide)
+    # the wide entries come last in the compiled list
+    assert [m for m, _ in fftc.compiled_lists(dtype)][-3:] == [n] * 3
+    rs, m = fftc.factorize(n, dtype)
+    assert m == 0 and tuple(rs) == wide[0]
+    bads = ([8, 8, 8, 8, 8], [2, 16, 16, 16, 4]) if dtype == "c64" else ([4, 4, 4, 16, 16], [2, 8, 16, 16, 4])
+    for bad in bads:
+        assert int(np.prod(bad)) == n
+        with pytest.raises(fftc.FFTCError) as e:
+            fftc.Plan(n, 2, radices=bad, dtype=dtype)
+        assert e.value.status == 2 and "compiled radix lists" in str(e.value)
 
 
 @pytest.mark.parametrize("n", [0, -4, 11, 13 * 4, (1 << 20) * 2, 3 ** 13])

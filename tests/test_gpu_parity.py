@@ -119,7 +119,8 @@ def test_config2_full_size_sampled(n, dtype):
         assert rel.max() <= 2 * tol_for(n, dtype), rel.max()
 
 
-@pytest.mark.parametrize("n,dtype", [(8192, "c64"), (16384, "c64"), (4096, "c128"), (8192, "c128")])
+@pytest.mark.parametrize("n,dtype", [(8192, "c64"), (16384, "c64"), (32768, "c64"), (4096, "c128"), (8192, "c128"),
+                                     (16384, "c128")])
 def test_half_exchange_full_size_sampled(n, dtype):
     # the lengths whose kernels exchange real and imaginary parts through LDS
     # separately, at the benchmarked launch size (2^24 elements, several
@@ -139,6 +140,20 @@ def test_half_exchange_full_size_sampled(n, dtype):
         ex = (np.abs(x.astype(np.complex128)) ** 2).sum(axis=1) * n
         ey = (np.abs(y.astype(np.complex128)) ** 2).sum(axis=1)
         assert (np.abs(ey - ex) / ex).max() <= 2 * tol_for(n, dtype)
+
+
+@pytest.mark.parametrize("n,dtype", [(32768, "c64"), (16384, "c128")])
+def test_wide_length_default_plan(n, dtype):
+    # past fftc_max_single_n: one kernel with the first compiled wide list,
+    # in place bit-identical to out of place, against the oracle
+    wide = [list(rs) for m, rs in fftc.compiled_lists(dtype) if m == n]
+    for d in (FWD, INV):
+        err, desc = check(n, 3, d, dtype, seed=4)
+        assert desc["variant"] == "single_specialised" and desc["radices"] == wide[0], desc
+        assert desc["split_m"] == 0 and desc["scratch_bytes"] == 0, desc
+        x = synth.uniform_complex(synth.rng(92, n), (3, n), np_dtype(dtype))
+        with fftc.Plan(n, 3, d, dtype) as p:
+            assert np.array_equal(run_plan(p, x), run_plan(p, x, inplace=True))
 
 
 def test_inplace_single_kernel():

@@ -42,6 +42,7 @@ CASES = half_lists()
 def test_there_are_lists_to_check():
     ns = {(cs, n) for cs, n, _, _ in CASES}
     assert (8, 16384) in ns and (8, 8192) in ns and (16, 8192) in ns and (16, 4096) in ns
+    assert (8, 32768) in ns and (16, 16384) in ns  # the wide lengths
 
 
 @pytest.mark.parametrize("cs,n,rs,tpt", CASES)

@@ -50,7 +50,10 @@ def test_autotune_argument_checks_on_host():
         fftc.autotune(11, 4)
     assert e.value.status == 2
     with pytest.raises(fftc.FFTCError) as e:
-        fftc.autotune(1 << 15, 4)      # two-pass length: not a single-kernel candidate
+        fftc.autotune(1 << 16, 4)      # two-pass length: not a single-kernel candidate
+    assert e.value.status == 2
+    with pytest.raises(fftc.FFTCError) as e:
+        fftc.autotune(3 << 13, 4)      # past the single-kernel limit, no compiled wide list
     assert e.value.status == 2
     with pytest.raises(fftc.FFTCError) as e:
         fftc.autotune(64, 0)
