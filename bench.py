@@ -85,7 +85,10 @@ def parse():
                     help="comma-separated names of the extra workloads to run (default: all)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=10000.0)
-    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-hold", type=int, default=16,
+                    help="server hold_at with fusion: rounds admitted while this many requests run wait "
+                         "for the device to drain below it (0: launch at once)")
     return ap.parse_args()
 
 
@@ -672,7 +675,7 @@ def config5(args, torch, fftc, synth, fuse=True, rate=None, nreq=None):
     del block
     offs = g.integers(0, (1 << 27), size=nreq)
     budget = 64 << 30
-    srv.start(budget, n_streams=args.serve_streams, max_inflight=64, fuse=fuse)
+    srv.start(budget, n_streams=args.serve_streams, max_inflight=64, fuse=fuse, hold_at=args.serve_hold if fuse else 0)
     try:
         for n in sorted(set(int(v) for v in reqs["n"])):
             for d in (fftc.FORWARD, fftc.INVERSE):
@@ -729,8 +732,10 @@ def config5(args, torch, fftc, synth, fuse=True, rate=None, nreq=None):
     by = float(sum(16.0 * int(n) * int(b) for n, b in zip(reqs["n"], reqs["batch"])))
     span = (max(c["done_ns"] for c in done.values()) - min(int(s) for s in sched)) * 1e-9
     return {"workload": f"{N} complex64 requests, Poisson arrivals at {rate:.0f}/s, "
-                        "batch U[1,256], N in 2^6..2^16, half forward / half inverse, budget 64 GiB, "
-                        + ("same-length requests admitted together fused into one launch" if fuse
+                        f"batch U[1,256], N in 2^6..2^16, half forward / half inverse, budget 64 GiB, "
+                        f"{args.serve_streams} streams, 64 slots, "
+                        + (f"same-length requests admitted together fused into one launch, rounds admitted "
+                           f"while {args.serve_hold} or more run held until fewer do" if fuse
                            else "one launch per request"),
             "fused_launches": st["fused_launches"] - st0["fused_launches"],
             "fused_requests": st["fused_requests"] - st0["fused_requests"],
@@ -750,7 +755,8 @@ def serving_sweep(args, torch, fftc, synth):
     for mult in (1, 2, 4, 8, 16, 32):
         r = config5(args, torch, fftc, synth, rate=mult * args.serve_rate, nreq=10000)
         out[f"{mult * args.serve_rate:.0f}"] = {k: r[k] for k in ("p50_us", "p99_us", "queue_p99_us",
-                                                                  "sustained_hbm_gbs", "offered_gbs")}
+                                                                  "sustained_hbm_gbs", "offered_gbs",
+                                                                  "fused_launches", "fused_requests")}
     return {"workload": "10000 complex64 requests per rate, the serving mix, fused admission",
             "fixed_rate_per_s": args.serve_rate, "by_rate_per_s": out}
 

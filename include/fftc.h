@@ -458,6 +458,11 @@ typedef struct {
     const char *tune_db;   /* tuning database file merged into the process's database
                               before any plan is made (NULL or "": none; a file that
                               cannot be read fails the start with FFTC_ERR_INVALID_ARG) */
+    int hold_at;           /* 0: an admitted request launches at once; k > 0: requests
+                              admitted while k or more are on the GPU wait, holding their
+                              slots and outputs, and launch together as soon as fewer
+                              than k are (larger rounds for fuse under load; nothing
+                              waits below k) */
 } fftc_server_config;
 
 typedef struct {

@@ -18,6 +18,10 @@
 //    (n, direction, dtype) form one step: a single launch of the
 //    several-requests kernel (each request keeps its own input, output and
 //    batch), with every request's event recorded after it.
+//  - With `hold_at` = k > 0, a round admitted while k or more requests are
+//    on the device waits (with its slots and outputs) and launches with the
+//    later rounds as soon as fewer than k are: under load, rounds grow and
+//    more requests share a launch; below it, nothing waits.
 //  - A host-only mock executor (no HIP calls, no computation) replaces the
 //    device for testing admission and scheduling on a CPU.
 #include <string.h>
@@ -421,6 +425,7 @@ class Server {
         // query); the mock executor's work and failed launches in `other`
         std::vector<std::deque<std::pair<InFlight, int>>> by_stream(std::max<size_t>(streams_.size(), 1));
         std::vector<std::pair<InFlight, int>> other;
+        std::vector<std::pair<InFlight, int>> held;  // admitted, waiting for the device to drain (hold_at)
         auto n_running = [&]() {
             size_t k = other.size();
             for (auto& q : by_stream) k += q.size();
@@ -481,8 +486,20 @@ class Server {
                     free_slots.pop_back();
                     ++stats_.admitted;
                 }
-                running_count_ = (int)(n_running() + to_launch.size());
+                running_count_ = (int)(n_running() + held.size() + to_launch.size());
                 stats_.max_inflight_seen = std::max<int>(stats_.max_inflight_seen, running_count_);
+            }
+            // continuous batching under load: while hold_at or more requests
+            // are on the device, admitted requests wait (holding their slots
+            // and outputs) and launch as one round when it drains below that,
+            // so more of them share a length and run fused
+            if (cfg_.hold_at > 0 && !stopping && (int)n_running() >= cfg_.hold_at) {
+                if (!to_launch.empty()) progressed = true;
+                held.insert(held.end(), to_launch.begin(), to_launch.end());
+                to_launch.clear();
+            } else if (!held.empty()) {
+                to_launch.insert(to_launch.begin(), held.begin(), held.end());  // arrival order
+                held.clear();
             }
             launch_round(to_launch);
             for (auto& fl : to_launch) {
@@ -543,7 +560,7 @@ class Server {
                 }
                 const size_t nrun = n_running();
                 running_count_ = (int)nrun;
-                if (stop_ && nrun == 0 && incoming_.empty() && pending_.empty()) break;
+                if (stop_ && nrun == 0 && held.empty() && incoming_.empty() && pending_.empty()) break;
                 // idle, or the queue head waits for memory or a slot: sleep
                 // until a submit, release or stop (or a short timeout)
                 if (!progressed && nrun == 0) {

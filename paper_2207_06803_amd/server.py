@@ -12,7 +12,8 @@ EXECUTOR_MOCK = 1
 
 class Config(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("n_streams", _int), ("max_inflight", _int),
-                ("executor", _int), ("mock_ns_per_mb", _i64), ("fuse", _int), ("tune_db", ctypes.c_char_p)]
+                ("executor", _int), ("mock_ns_per_mb", _i64), ("fuse", _int), ("tune_db", ctypes.c_char_p),
+                ("hold_at", _int)]
 
 
 class Request(ctypes.Structure):
@@ -51,10 +52,11 @@ def now_ns() -> int:
     return int(lib.fftc_now_ns())
 
 
-def start(budget_bytes: int, n_streams: int = 4, max_inflight: int = 64,
-          executor: int = EXECUTOR_GPU, mock_ns_per_mb: int = 0, fuse: bool = False, tune_db: str = None) -> None:
+def start(budget_bytes: int, n_streams: int = 8, max_inflight: int = 64,
+          executor: int = EXECUTOR_GPU, mock_ns_per_mb: int = 0, fuse: bool = False, tune_db: str = None,
+          hold_at: int = 0) -> None:
     cfg = Config(budget_bytes, n_streams, max_inflight, executor, mock_ns_per_mb, 1 if fuse else 0,
-                 tune_db.encode() if tune_db else None)
+                 tune_db.encode() if tune_db else None, hold_at)
     check(lib.fftc_server_start(ctypes.byref(cfg)), "fftc_server_start")
 
 

@@ -193,3 +193,31 @@ def test_server_config_tune_db(tmp_path):
         assert e.value.status == 1
     finally:
         fftc.tune_clear()
+
+
+@pytest.mark.parametrize("hold_at", [0, 2])
+def test_hold_at_launches_held_rounds_when_the_device_drains(hold_at):
+    """hold_at = k: requests admitted while k or more are running wait and
+    start once fewer than k run; hold_at = 0 starts every request at
+    admission.  Two 1 MiB requests run 50 ms each (mock executor); two more
+    arrive 10 ms later."""
+    srv.start(64 << 20, n_streams=2, max_inflight=16, executor=srv.EXECUTOR_MOCK,
+              mock_ns_per_mb=50_000_000, hold_at=hold_at)
+    try:
+        for tag in (0, 1):
+            assert srv.submit(1024, 128, fftc.FORWARD, FAKE_IN, tag) == 0
+        time.sleep(0.010)
+        for tag in (2, 3):
+            assert srv.submit(1024, 128, fftc.FORWARD, FAKE_IN, tag) == 0
+        got = {c["tag"]: c for c in _drain(4)}
+        assert sorted(got) == [0, 1, 2, 3] and all(c["status"] == 0 for c in got.values())
+        first_done = min(got[0]["done_ns"], got[1]["done_ns"])
+        late = [got[2]["start_ns"], got[3]["start_ns"]]
+        if hold_at:
+            assert min(late) >= first_done
+        else:
+            assert max(late) < first_done
+        for c in got.values():
+            assert c["arrival_ns"] <= c["admit_ns"] <= c["start_ns"] <= c["done_ns"]
+    finally:
+        srv.stop(drain=True)
