@@ -80,7 +80,7 @@ def parse():
                          "(TCC_EA0_RDREQ, _32B, _64B, _128B) that pins the FETCH_SIZE scale, then exit")
     ap.add_argument("--profile-set", default="",
                     help="only launch the named hot-path kernels a few times each, for counter runs: comma-separated "
-                         "from mixed, split, two_pass, c64_16384, wave256, copy")
+                         "from mixed, split, two_pass, wide, c64_16384, wave256, copy")
     ap.add_argument("--extras", default="",
                     help="comma-separated names of the extra workloads to run (default: all)")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -299,7 +299,9 @@ def c128(torch, fftc, synth, timer):
     ys = [torch.empty_like(x0) for _ in range(NBUF)]
     del x0
     out = {}
-    for n in SIZES:
+    # the headline lengths, then the half-width exchange lengths (8192: two
+    # workgroups per CU; 16384: one kernel instead of two passes)
+    for n in tuple(SIZES) + (8192, 16384):
         for d in (fftc.FORWARD, fftc.INVERSE):
             with fftc.Plan(n, ELEMS // n, d, "c128") as p:
                 avg = timer.avg_ms(lambda i, p=p: p.execute(xs[i % NBUF], ys[i % NBUF], timer.s), 10)
@@ -841,13 +843,21 @@ def profile_set(names, torch, fftc, synth):
                     launches(f"{mode} N={n} batch {b}", [p], xs, ys, 3)
             del x, xs, ys
             torch.cuda.empty_cache()
-    if "two_pass" in names or "c64_16384" in names:
+    if "two_pass" in names or "c64_16384" in names or "wide" in names:
         x = torch.from_numpy(synth.uniform_complex(synth.rng(1, 0), (ELEMS,), np.complex64)).to("cuda")
         xs = [x] + [x.clone() for _ in range(NBUF - 1)]
         ys = [torch.empty_like(x) for _ in range(NBUF)]
-        for n in ((1 << 20, 65536, 32768) if "two_pass" in names else ()) + ((16384,) if "c64_16384" in names else ()):
+        for n in (((1 << 20, 65536) if "two_pass" in names else ()) + ((32768,) if "wide" in names else ())
+                  + ((16384,) if "c64_16384" in names else ())):
             with fftc.Plan(n, ELEMS // n, fftc.FORWARD, "c64") as p:
                 launches(f"c64 N={n} batch {ELEMS // n} ({p.describe()['variant']})", [p], xs, ys, 3)
+        del x, xs, ys
+    if "wide" in names:  # complex128 N = 16384 in one kernel
+        x = torch.from_numpy(synth.uniform_complex(synth.rng(1, 1), (ELEMS,), np.complex128)).to("cuda")
+        xs = [x] + [x.clone() for _ in range(NBUF - 1)]
+        ys = [torch.empty_like(x) for _ in range(NBUF)]
+        with fftc.Plan(16384, ELEMS // 16384, fftc.FORWARD, "c128") as p:
+            launches(f"c128 N=16384 batch {ELEMS // 16384} ({p.describe()['variant']})", [p], xs, ys, 3)
         del x, xs, ys
     if "wave256" in names:
         x = torch.from_numpy(synth.uniform_complex(synth.rng(8), (ELEMS,), np.complex64)).to("cuda")
