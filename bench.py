@@ -85,7 +85,7 @@ def parse():
                     help="comma-separated names of the extra workloads to run (default: all)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=10000.0)
-    ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-streams", type=int, default=16)
     ap.add_argument("--serve-hold", type=int, default=16,
                     help="server hold_at with fusion: rounds admitted while this many requests run wait "
                          "for the device to drain below it (0: launch at once)")
