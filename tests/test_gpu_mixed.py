@@ -125,3 +125,21 @@ def test_autotune_records_choice():
                 assert p.describe()["radices"] == rs
     finally:
         fftc.tune_clear()
+
+
+@pytest.mark.parametrize("n,dtype", [(32768, "c64"), (16384, "c128")])
+def test_autotune_wide_length_times_its_compiled_lists(n, dtype):
+    # past fftc_max_single_n the autotuner times the compiled wide lists only;
+    # its pick is recorded and later plans run it as one kernel
+    wide = [list(rs) for m, rs in fftc.compiled_lists(dtype) if m == n]
+    fftc.tune_clear()
+    try:
+        rs, us = fftc.autotune(n, 4, dtype, reps=5)
+        say(f"autotune n={n} {dtype} -> {rs} {us:.2f} us")
+        assert rs in wide and us > 0
+        assert fftc.factorize(n, dtype)[0] == rs
+        with fftc.Plan(n, 2, fftc.FORWARD, dtype) as p:
+            d = p.describe()
+            assert d["radices"] == rs and d["variant"] == "single_specialised", d
+    finally:
+        fftc.tune_clear()
