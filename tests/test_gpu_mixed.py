@@ -143,3 +143,37 @@ def test_autotune_wide_length_times_its_compiled_lists(n, dtype):
             assert d["radices"] == rs and d["variant"] == "single_specialised", d
     finally:
         fftc.tune_clear()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_every_compiled_body_in_a_mixed_plan(dtype, tmp_path):
+    # every compiled list of the mixed lengths (N <= 4096) runs as a body of
+    # the persistent kernel: round k records the k-th compiled list of each
+    # length in the tuning database, plans a mixed list of those lengths (a
+    # ragged count of each) and checks it against the oracle
+    by_n = {}
+    for n, rs in fftc.compiled_lists(dtype):
+        if 2 <= n <= 4096:
+            by_n.setdefault(n, []).append(rs)
+    rounds = max(len(v) for v in by_n.values())
+    key = fftc.tune_key()
+    saved = str(tmp_path / "saved.tune")
+    fftc.tune_save(saved)
+    try:
+        for k in range(rounds):
+            ns = sorted(n for n, v in by_n.items() if k < len(v))
+            db = tmp_path / f"round{k}.tune"
+            db.write_text("".join(f"{key} {dtype} {n} {','.join(map(str, by_n[n][k]))} 1.0\n" for n in ns))
+            fftc.tune_clear()
+            assert fftc.tune_load(str(db)) == len(ns)
+            lengths = np.array([n for i, n in enumerate(ns) for _ in range(1 + (i + k) % 3)], dtype=np.int64)
+            g = synth.rng(150, k, 1 if dtype == "c128" else 0)
+            x = synth.uniform_complex(g, (int(lengths.sum()),), np_dtype(dtype))
+            d = fftc.FORWARD if k % 2 == 0 else fftc.INVERSE
+            say(f"mixed bodies round {k}: {len(ns)} lengths, {len(lengths)} transforms, {dtype}, dir {d}")
+            with fftc.plan_mixed(lengths, d, dtype) as p:
+                y = run(p, x)
+            check_mixed_output(lengths, x, y, d, dtype)
+    finally:
+        fftc.tune_clear()
+        fftc.tune_load(saved)
