@@ -85,7 +85,8 @@ def parse():
                     help="comma-separated names of the extra workloads to run (default: all)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=10000.0)
-    ap.add_argument("--serve-streams", type=int, default=16)
+    ap.add_argument("--serve-streams", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=256, help="server max_inflight (requests on the GPU at once)")
     ap.add_argument("--serve-hold", type=int, default=16,
                     help="server hold_at with fusion: rounds admitted while this many requests run wait "
                          "for the device to drain below it (0: launch at once)")
@@ -677,7 +678,8 @@ def config5(args, torch, fftc, synth, fuse=True, rate=None, nreq=None):
     del block
     offs = g.integers(0, (1 << 27), size=nreq)
     budget = 64 << 30
-    srv.start(budget, n_streams=args.serve_streams, max_inflight=64, fuse=fuse, hold_at=args.serve_hold if fuse else 0)
+    srv.start(budget, n_streams=args.serve_streams, max_inflight=args.serve_slots, fuse=fuse,
+              hold_at=args.serve_hold if fuse else 0)
     try:
         for n in sorted(set(int(v) for v in reqs["n"])):
             for d in (fftc.FORWARD, fftc.INVERSE):
@@ -735,7 +737,7 @@ def config5(args, torch, fftc, synth, fuse=True, rate=None, nreq=None):
     span = (max(c["done_ns"] for c in done.values()) - min(int(s) for s in sched)) * 1e-9
     return {"workload": f"{N} complex64 requests, Poisson arrivals at {rate:.0f}/s, "
                         f"batch U[1,256], N in 2^6..2^16, half forward / half inverse, budget 64 GiB, "
-                        f"{args.serve_streams} streams, 64 slots, "
+                        f"{args.serve_streams} streams, {args.serve_slots} slots, "
                         + (f"same-length requests admitted together fused into one launch, rounds admitted "
                            f"while {args.serve_hold} or more run held until fewer do" if fuse
                            else "one launch per request"),

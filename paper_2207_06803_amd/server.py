@@ -52,7 +52,7 @@ def now_ns() -> int:
     return int(lib.fftc_now_ns())
 
 
-def start(budget_bytes: int, n_streams: int = 16, max_inflight: int = 64,
+def start(budget_bytes: int, n_streams: int = 64, max_inflight: int = 256,
           executor: int = EXECUTOR_GPU, mock_ns_per_mb: int = 0, fuse: bool = False, tune_db: str = None,
           hold_at: int = 0) -> None:
     cfg = Config(budget_bytes, n_streams, max_inflight, executor, mock_ns_per_mb, 1 if fuse else 0,
