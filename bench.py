@@ -368,6 +368,11 @@ def config3(torch, fftc, synth, timer):
         for k in range(NBUF):  # each plan keeps its own buffer pair (no graph update per launch)
             mplans[k].execute(xs[k], ys[k], timer.s)
         mixed_ms = timer.avg_ms(lambda i: mplans[i % NBUF].execute(xs[i % NBUF], ys[i % NBUF], timer.s), 48)
+        # the same launches without the graph: each replay leaves the GPU idle
+        # a few microseconds before the kernel starts
+        for q in mplans:
+            q.set_mixed_launch(fftc.MIXED_LAUNCH_DIRECT)
+        direct_ms = timer.avg_ms(lambda i: mplans[i % NBUF].execute(xs[i % NBUF], ys[i % NBUF], timer.s), 48)
         # per-length path: the same transforms grouped by length, 37 batched plans
         uniq, counts = np.unique(lengths, return_counts=True)
         plans = [fftc.Plan(int(n), int(c), fftc.FORWARD, "c64") for n, c in zip(uniq, counts)]
@@ -397,6 +402,8 @@ def config3(torch, fftc, synth, timer):
             "persistent_us": mixed_ms * 1e3, "persistent_gflops": fl / (mixed_ms * 1e-3) / 1e9,
             "persistent_hbm_gbs": 16 * tot / (mixed_ms * 1e-3) / 1e9,
             "persistent_roofline_frac": 16 * tot / (mixed_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "persistent_direct_us": direct_ms * 1e3,
+            "persistent_direct_roofline_frac": 16 * tot / (direct_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "per_length_graph_us": graph_ms * 1e3, "per_length_eager_us": eager_ms * 1e3,
             "speedup_vs_per_length_graph": graph_ms / mixed_ms,
             "work_items": d["mixed_items"], "persistent_groups": d["persistent_groups"],

@@ -335,6 +335,20 @@ fftc_status fftc_plan_mixed(const int64_t *n, int64_t count, int direction, int 
                             fftc_plan_t *plan_out);
 
 /*
+ * How fftc_execute runs a mixed plan's persistent launch:
+ * FFTC_MIXED_LAUNCH_GRAPH (the default) replays the plan's instantiated
+ * hipGraph; FFTC_MIXED_LAUNCH_DIRECT launches the same kernel with the same
+ * arguments on the stream (a caller can still capture that launch into a
+ * graph of its own).  Results are identical.  Measured on MI355X, a replay
+ * leaves the GPU idle about 8 us before the kernel starts, where back-to-back
+ * direct launches leave no gap.  FFTC_ERR_INVALID_ARG for a NULL or non-mixed
+ * plan or another mode.  Host-only; not while an execution is being enqueued
+ * on the plan from another thread.
+ */
+enum { FFTC_MIXED_LAUNCH_GRAPH = 0, FFTC_MIXED_LAUNCH_DIRECT = 1 };
+fftc_status fftc_plan_mixed_set_launch(fftc_plan_t plan, int mode);
+
+/*
  * Autotuner (the planner the paper names as missing, Section VI; different
  * factorisations suit different hardware, Section I).  Times every
  * candidate Stockham radix list for single-kernel length n (for a wide

@@ -476,6 +476,17 @@ fftc_status fftc_plan_mixed(const int64_t* n, int64_t count, int direction, int 
     }
 }
 
+fftc_status fftc_plan_mixed_set_launch(fftc_plan_t p, int mode) {
+    clear_error();
+    if (!p) return fail(FFTC_ERR_INVALID_ARG, "plan is NULL");
+    if (p->variant != FFTC_VARIANT_MIXED_PERSISTENT || !p->mixed)
+        return fail(FFTC_ERR_INVALID_ARG, "not a mixed plan");
+    if (mode != FFTC_MIXED_LAUNCH_GRAPH && mode != FFTC_MIXED_LAUNCH_DIRECT)
+        return fail(FFTC_ERR_INVALID_ARG, "mode must be FFTC_MIXED_LAUNCH_GRAPH or FFTC_MIXED_LAUNCH_DIRECT");
+    p->mixed->direct = mode == FFTC_MIXED_LAUNCH_DIRECT;
+    return FFTC_OK;
+}
+
 static fftc_status execute_impl(fftc_plan_t p, const void* in, void* out, int64_t batch, void* stream) {
     clear_error();
     if (!p) return fail(FFTC_ERR_INVALID_ARG, "plan is NULL");

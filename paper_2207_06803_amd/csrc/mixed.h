@@ -56,6 +56,8 @@ struct MixedState {
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t kernel_node = nullptr;
     const void* fn = nullptr;
+    bool direct = false;       // launch the kernel on the stream instead of replaying the graph
+    bool graph_stale = false;  // a direct launch changed args after the graph's parameters were set
     MixedArgs args{};
     void* kargs[7] = {};
     std::vector<int64_t> class_len;

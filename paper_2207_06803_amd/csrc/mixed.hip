@@ -223,7 +223,17 @@ hipKernelNodeParams MixedState::kernel_params(const void* fn_) {
 
 fftc_status launch_mixed(fftc_plan_s* p, const void* in, void* out, hipStream_t s) {
     MixedState* m = p->mixed;
-    if (in != m->args.in || out != m->args.out) {
+    if (m->direct) {  // the same kernel and arguments, launched on the stream
+        m->args.in = in;
+        m->args.out = out;
+        hipKernelNodeParams kp = m->kernel_params(m->fn);
+        FFTC_HIP_TRY(hipLaunchKernel(kp.func, kp.gridDim, kp.blockDim, kp.kernelParams, kp.sharedMemBytes, s));
+        // the graph's pointer arguments no longer match args: refresh them on the next replay
+        m->graph_stale = true;
+        return FFTC_OK;
+    }
+    if (in != m->args.in || out != m->args.out || m->graph_stale) {
+        m->graph_stale = false;
         m->args.in = in;
         m->args.out = out;
         hipKernelNodeParams kp = m->kernel_params(m->fn);

@@ -38,6 +38,8 @@ ORDER_PEASE = 2
 ORDER_FOURSTEP = 3
 ORDER_WAVE = 4
 ORDER_NAMES = {0: "stockham", 1: "ct", 2: "pease", 3: "fourstep", 4: "wave"}
+MIXED_LAUNCH_GRAPH = 0
+MIXED_LAUNCH_DIRECT = 1
 
 # formula plan flags
 FORMULA_NO_FOLD = 1
@@ -92,6 +94,7 @@ _SIGNATURES = {
                                    ctypes.POINTER(_int)]),
     "fftc_candidates": (_int, [_i64, ctypes.POINTER(_int), ctypes.POINTER(_int), _int, ctypes.POINTER(_int)]),
     "fftc_plan_mixed": (_int, [ctypes.POINTER(_i64), _i64, _int, _int, ctypes.POINTER(_vp)]),
+    "fftc_plan_mixed_set_launch": (_int, [_vp, _int]),
     "fftc_autotune": (_int, [_i64, _i64, _int, _int, ctypes.POINTER(_int), _int, ctypes.POINTER(_int),
                              ctypes.POINTER(ctypes.c_double)]),
     "fftc_tune_load": (_int, [ctypes.c_char_p, ctypes.POINTER(_int)]),
@@ -303,6 +306,11 @@ class Plan:
             check_extent(y, nout, "output", self.device)
         check(lib.fftc_execute_batch(self._h, ptr(x), ptr(y), int(batch), stream_handle(stream)),
               "fftc_execute_batch")
+
+    def set_mixed_launch(self, mode: int) -> None:
+        """Mixed plans: MIXED_LAUNCH_GRAPH (replay the plan's hipGraph, the
+        default) or MIXED_LAUNCH_DIRECT (launch the same kernel on the stream)."""
+        check(lib.fftc_plan_mixed_set_launch(self._h, int(mode)), "fftc_plan_mixed_set_launch")
 
     def describe(self) -> dict:
         d = PlanDesc()

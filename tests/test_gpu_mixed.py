@@ -87,6 +87,42 @@ def test_mixed_equals_per_length_plans():
         assert rel_l2(ys, yd.cpu().numpy()).max() <= 1e-6, n
 
 
+def test_direct_launch_matches_graph_replay():
+    # the same kernel launched on the stream instead of replayed from the
+    # plan's graph: bit-identical outputs, also across pointer changes and a
+    # switch back to the graph (whose pointer arguments must follow)
+    g = synth.rng(97)
+    lengths = synth.draw_mixed_sizes(g, 1500)
+    tot = int(lengths.sum())
+    xa = torch.from_numpy(synth.uniform_complex(g, (tot,), np.complex64)).to("cuda")
+    xb = torch.from_numpy(synth.uniform_complex(g, (tot,), np.complex64)).to("cuda")
+    with fftc.plan_mixed(lengths, fftc.INVERSE) as p:
+        ya, yb = torch.empty_like(xa), torch.empty_like(xb)
+        p.execute(xa, ya)
+        p.execute(xb, yb)
+        torch.cuda.synchronize()
+        ref_a, ref_b = ya.cpu().numpy(), yb.cpu().numpy()
+        p.set_mixed_launch(fftc.MIXED_LAUNCH_DIRECT)
+        for rep in range(3):
+            ya.zero_(), yb.zero_()
+            p.execute(xb, yb)
+            p.execute(xa, ya)
+            torch.cuda.synchronize()
+            assert np.array_equal(ya.cpu().numpy(), ref_a) and np.array_equal(yb.cpu().numpy(), ref_b), rep
+        p.set_mixed_launch(fftc.MIXED_LAUNCH_GRAPH)
+        # the graph's parameters were last set for (xb, yb); the last direct
+        # launch used (xa, ya), so this replay must update them
+        ya.zero_(), yb.zero_()
+        p.execute(xa, ya)
+        torch.cuda.synchronize()
+        assert np.array_equal(ya.cpu().numpy(), ref_a) and not yb.cpu().numpy().any()
+        with pytest.raises(fftc.FFTCError):
+            p.set_mixed_launch(7)
+    with fftc.Plan(64, 4) as q:
+        with pytest.raises(fftc.FFTCError):
+            q.set_mixed_launch(fftc.MIXED_LAUNCH_DIRECT)  # not a mixed plan
+
+
 def test_graph_replays_and_pointer_changes():
     g = synth.rng(98)
     lengths = synth.draw_mixed_sizes(g, 2000)

@@ -60,6 +60,10 @@ def test_autotune_argument_checks_on_host():
     assert e.value.status == 1
 
 
+def test_mixed_launch_mode_argument_checks_on_host():
+    assert fftc.lib.fftc_plan_mixed_set_launch(None, fftc.MIXED_LAUNCH_DIRECT) == 1  # NULL plan
+
+
 def test_mixed_plan_argument_checks_on_host():
     for bad in ([8, 11], [8, 8192], [0], []):
         with pytest.raises(fftc.FFTCError) as e:
