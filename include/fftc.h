@@ -327,7 +327,7 @@ fftc_status fftc_copy(const void *in, void *out, size_t bytes, void *stream);
  * descriptor while it runs the current one.  The
  * launch is recorded in a hipGraph at plan time; fftc_execute replays it on
  * the caller's stream (updating the graph's pointer arguments when in/out
- * change).  Executions of one mixed plan on different streams must not
+ * change), or launches the kernel directly (fftc_plan_mixed_set_launch).  Executions of one mixed plan on different streams must not
  * overlap: they share the plan's one instantiated graph, whose pointer
  * arguments a call with other in/out updates.
  */
