@@ -397,7 +397,8 @@ def config3(torch, fftc, synth, timer):
         fftc.tune_load(saved)
         os.unlink(saved)
     return {"workload": "10,000 complex64 transforms, 37 lengths 8..4096 (2^k, 3*2^k, 5*2^k, 7*2^k), "
-                        "one persistent launch in a hipGraph, four rotating copies of the list",
+                        "one persistent launch replayed from its hipGraph (persistent_*) and launched "
+                        "directly (persistent_direct_*), four rotating copies of the list",
             "elements": tot, "bytes": 16 * tot, "gflop": fl / 1e9,
             "persistent_us": mixed_ms * 1e3, "persistent_gflops": fl / (mixed_ms * 1e-3) / 1e9,
             "persistent_hbm_gbs": 16 * tot / (mixed_ms * 1e-3) / 1e9,
