@@ -60,9 +60,12 @@ def gpu_server():
             pass
 
 
-@pytest.mark.parametrize("fuse", [False, True])
-def test_results_in_the_mix_equal_results_alone(gpu_server, fuse):
-    gpu_server(1 << 30, n_streams=4, max_inflight=32, fuse=fuse)
+@pytest.mark.parametrize("fuse,hold_at", [(False, 0), (True, 0), (True, 4)])
+def test_results_in_the_mix_equal_results_alone(gpu_server, fuse, hold_at):
+    # hold_at = 4: rounds admitted while 4 or more requests run wait and
+    # launch together (larger fused steps); every result must still equal the
+    # same request run alone, bit for bit
+    gpu_server(1 << 30, n_streams=4, max_inflight=32, fuse=fuse, hold_at=hold_at)
     g = synth.rng(5, 1)
     pool = torch.from_numpy(synth.uniform_complex(g, (1 << 21,), np.complex64)).to("cuda")
     reqs = []
